@@ -1,0 +1,547 @@
+/*
+ * vmt_oracle.c -- plain scalar CPU reference for the V-family generators.
+ *
+ * TEST INFRASTRUCTURE: see vmt_oracle.h. Only the tests, the smoke check and
+ * the benchmark's CPU-baseline leg use this file. It shares nothing with the
+ * product library.
+ *
+ * Parity status of each function (what pins it is in tests/test_oracle_*.py):
+ *   MT19937-32/-64 recurrence, tempering, init_genrand: pinned by the C++
+ *     standard library engines (std::mt19937 / std::mt19937_64) and the
+ *     10000th-output values required by the C++ standard.
+ *   MT19937-32 init_by_array: pinned by numpy RandomState(uint32 array) and
+ *     CPython random.seed (both seed by init_by_array).
+ *   SFMT19937 recurrence: pinned structurally (the minimal polynomial of the
+ *     map must carry an irreducible factor of degree 19937); value-level
+ *     output for a given seed: parity unpinned (no published check output is
+ *     available here).
+ *   SFMT19937 seeding / period certification constants: pinned algebraically
+ *     (the parity vector must annihilate the complement of the degree-19937
+ *     component); the bit-exact seeded state itself: parity unpinned.
+ *   Minimal polynomial, powers of t, jump: pinned by brute-force stepping,
+ *     composition, the period identity and the Frobenius identity.
+ */
+#include "vmt_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Parameters. Sec. 2.2 eq. (params), Sec. 2.3 eq. (params64),              */
+/* Sec. 2.4 eq. (sfmt_params).                                               */
+/* ------------------------------------------------------------------------ */
+
+/* MT19937-32: (w, n, m, r) = (32, 624, 397, 31). h keeps the w - r = 1 top
+ * bit, l the r = 31 low bits (Sec. 2.1 definition of h and l). */
+#define MT32_N 624
+#define MT32_M 397
+#define MT32_H 0x80000000u
+#define MT32_L 0x7fffffffu
+#define MT32_A 0x9908B0DFu
+
+/* MT19937-64: (w, n, m, r) = (64, 312, 156, 31): omega takes 33 bits from
+ * x_k and 31 from x_{k+1}. */
+#define MT64_N 312
+#define MT64_M 156
+#define MT64_H 0xFFFFFFFF80000000ull
+#define MT64_L 0x000000007FFFFFFFull
+#define MT64_A 0xB5026F5AA96619E9ull
+
+/* SFMT19937: N = 156 128-bit words, m = 122, mask K. */
+#define SFMT_N 156
+#define SFMT_M 122
+static const uint32_t SFMT_K[4] = {0xDFFFFFEFu, 0xDDFECB7Fu, 0xBFFAFFFFu, 0xBFFFFFF6u};
+/* Period-certification parity vector of the published SFMT19937 parameter
+ * set (not in the paper; checked algebraically by the tests). */
+static const uint32_t SFMT_PARITY[4] = {0x00000001u, 0x00000000u, 0x00000000u, 0x13c9e684u};
+
+int or_state_words(int variant) {
+    return variant == 0 ? MT32_N : variant == 1 ? MT64_N : SFMT_N;
+}
+int or_word_bytes(int variant) {
+    return variant == 0 ? 4 : variant == 1 ? 8 : 16;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Seeding. The paper starts from "a certain initial state" and gives no      */
+/* seeding rule; these are the base generators' published initialisations.  */
+/* ------------------------------------------------------------------------ */
+
+void or_mt32_init_genrand(uint32_t x[624], uint32_t seed) {
+    x[0] = seed;
+    for (uint32_t i = 1; i < MT32_N; i++)
+        x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+}
+
+/* init_by_array of Matsumoto-Nishimura's MT19937 release:
+ * start from init_genrand(19650218); one pass of max(n, key_len) steps mixes
+ * in the key, a second pass of n - 1 steps stirs, word 0 is set to 2^31. */
+void or_mt32_init_by_array(uint32_t x[624], const uint32_t* key, int key_len) {
+    or_mt32_init_genrand(x, 19650218u);
+    int i = 1, j = 0;
+    int steps = MT32_N > key_len ? MT32_N : key_len;
+    for (int s = 0; s < steps; s++) {
+        uint32_t prev = x[i - 1];
+        x[i] = (x[i] ^ ((prev ^ (prev >> 30)) * 1664525u)) + key[j] + (uint32_t)j;
+        i++;
+        j++;
+        if (i >= MT32_N) {
+            x[0] = x[MT32_N - 1];
+            i = 1;
+        }
+        if (j >= key_len) j = 0;
+    }
+    for (int s = 0; s < MT32_N - 1; s++) {
+        uint32_t prev = x[i - 1];
+        x[i] = (x[i] ^ ((prev ^ (prev >> 30)) * 1566083941u)) - (uint32_t)i;
+        i++;
+        if (i >= MT32_N) {
+            x[0] = x[MT32_N - 1];
+            i = 1;
+        }
+    }
+    x[0] = 0x80000000u;
+}
+
+void or_mt64_init_genrand(uint64_t x[312], uint64_t seed) {
+    x[0] = seed;
+    for (uint64_t i = 1; i < MT64_N; i++)
+        x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + i;
+}
+
+/* SFMT: MT32's init_genrand over the 624 32-bit sub-words (sub-word j of
+ * word k is index 4k + j), then period certification: if the parity of
+ * <PARITY, word 0> is even, flip the lowest set bit of PARITY in word 0. */
+int or_sfmt_init_genrand(uint32_t x[624], uint32_t seed) {
+    x[0] = seed;
+    for (uint32_t i = 1; i < 4 * SFMT_N; i++)
+        x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+    uint32_t inner = 0;
+    for (int j = 0; j < 4; j++) inner ^= x[j] & SFMT_PARITY[j];
+    int parity = 0;
+    for (int b = 0; b < 32; b++) parity ^= (int)((inner >> b) & 1u);
+    if (parity == 1) return 0;
+    for (int j = 0; j < 4; j++) {
+        for (int b = 0; b < 32; b++) {
+            if ((SFMT_PARITY[j] >> b) & 1u) {
+                x[j] ^= 1u << b;
+                return 1;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tempering, eq. (tempering); the first line tempers the new word itself.   */
+/* ------------------------------------------------------------------------ */
+
+uint32_t or_mt32_temper(uint32_t x) {
+    uint32_t y = x ^ ((x >> 11) & 0xFFFFFFFFu);
+    y = y ^ ((y << 7) & 0x9D2C5680u);
+    y = y ^ ((y << 15) & 0xEFC60000u);
+    return y ^ (y >> 18);
+}
+
+uint64_t or_mt64_temper(uint64_t x) {
+    uint64_t y = x ^ ((x >> 29) & 0x5555555555555555ull);
+    y = y ^ ((y << 17) & 0x71D67FFFEDA60000ull);
+    y = y ^ ((y << 37) & 0xFFF7EEE000000000ull);
+    return y ^ (y >> 43);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One recurrence step on a circular buffer, eq. (stepmod).                  */
+/* ------------------------------------------------------------------------ */
+
+/* eq. (step) with eq. (matmult): omega * A = omega >> 1, xor a if omega odd. */
+static uint32_t mt32_step(uint32_t* x, int* k) {
+    int i = *k;
+    uint32_t omega = (x[i] & MT32_H) | (x[(i + 1) % MT32_N] & MT32_L);
+    uint32_t omega_a = (omega >> 1) ^ ((omega & 1u) ? MT32_A : 0u);
+    uint32_t nw = x[(i + MT32_M) % MT32_N] ^ omega_a;
+    x[i] = nw;
+    *k = (i + 1) % MT32_N;
+    return nw;
+}
+
+static uint64_t mt64_step(uint64_t* x, int* k) {
+    int i = *k;
+    uint64_t omega = (x[i] & MT64_H) | (x[(i + 1) % MT64_N] & MT64_L);
+    uint64_t omega_a = (omega >> 1) ^ ((omega & 1ull) ? MT64_A : 0ull);
+    uint64_t nw = x[(i + MT64_M) % MT64_N] ^ omega_a;
+    x[i] = nw;
+    *k = (i + 1) % MT64_N;
+    return nw;
+}
+
+/* 128-bit values as (lo, hi) halves; sub-word 0 is the least significant. */
+static void u128_load(const uint32_t w[4], uint64_t* lo, uint64_t* hi) {
+    *lo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    *hi = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+}
+static void u128_store(uint32_t w[4], uint64_t lo, uint64_t hi) {
+    w[0] = (uint32_t)lo;
+    w[1] = (uint32_t)(lo >> 32);
+    w[2] = (uint32_t)hi;
+    w[3] = (uint32_t)(hi >> 32);
+}
+
+/* eq. (sfmt_step):
+ *   w_{k+N} = w_k ^ (w_k <<< 8) ^ ((w_{k+m} >> 11) & K) ^ (w_{k+N-2} >>> 8)
+ *             ^ (w_{k+N-1} << 18)
+ * <<< / >>> shift the whole 128-bit word, << / >> each 32-bit sub-word. */
+static void sfmt_step(uint32_t* x, int* k, uint32_t out[4]) {
+    int i = *k;
+    const uint32_t* a = x + 4 * i;
+    const uint32_t* b = x + 4 * ((i + SFMT_M) % SFMT_N);
+    const uint32_t* c = x + 4 * ((i + SFMT_N - 2) % SFMT_N);
+    const uint32_t* d = x + 4 * ((i + SFMT_N - 1) % SFMT_N);
+    uint64_t lo, hi;
+    uint32_t a_shl[4], c_shr[4], r[4];
+    u128_load(a, &lo, &hi);
+    u128_store(a_shl, lo << 8, (hi << 8) | (lo >> 56));
+    u128_load(c, &lo, &hi);
+    u128_store(c_shr, (lo >> 8) | (hi << 56), hi >> 8);
+    for (int j = 0; j < 4; j++)
+        r[j] = a[j] ^ a_shl[j] ^ ((b[j] >> 11) & SFMT_K[j]) ^ c_shr[j] ^ (d[j] << 18);
+    memcpy(x + 4 * i, r, sizeof r);
+    if (out) memcpy(out, r, sizeof r);
+    *k = (i + 1) % SFMT_N;
+}
+
+void or_step(int variant, void* buf, int* k, void* out, size_t count, int temper) {
+    for (size_t s = 0; s < count; s++) {
+        if (variant == 0) {
+            uint32_t v = mt32_step((uint32_t*)buf, k);
+            if (out) ((uint32_t*)out)[s] = temper ? or_mt32_temper(v) : v;
+        } else if (variant == 1) {
+            uint64_t v = mt64_step((uint64_t*)buf, k);
+            if (out) ((uint64_t*)out)[s] = temper ? or_mt64_temper(v) : v;
+        } else {
+            sfmt_step((uint32_t*)buf, k, out ? (uint32_t*)out + 4 * s : NULL);
+        }
+    }
+}
+
+void or_canon(int variant, const void* buf, int k, void* canon) {
+    int n = or_state_words(variant), wb = or_word_bytes(variant);
+    const unsigned char* src = (const unsigned char*)buf;
+    unsigned char* dst = (unsigned char*)canon;
+    for (int j = 0; j < n; j++) memcpy(dst + (size_t)j * wb, src + (size_t)((k + j) % n) * wb, wb);
+}
+
+/* ------------------------------------------------------------------------ */
+/* GF(2)[t]: bit i of the word array is the coefficient of t^i.              */
+/* ------------------------------------------------------------------------ */
+
+static int bit_get(const uint64_t* a, int i) { return (int)((a[i >> 6] >> (i & 63)) & 1u); }
+static void bit_flip(uint64_t* a, int i) { a[i >> 6] ^= 1ull << (i & 63); }
+
+int or_poly_deg(const uint64_t* a) {
+    for (int w = OR_PW - 1; w >= 0; w--) {
+        if (a[w]) {
+            for (int b = 63; b >= 0; b--)
+                if ((a[w] >> b) & 1u) return w * 64 + b;
+        }
+    }
+    return -1;
+}
+
+/* a ^= b * t^s (b must fit after the shift) */
+static void xor_shifted(uint64_t* a, const uint64_t* b, int deg_b, int s) {
+    int wo = s >> 6, bo = s & 63;
+    int nw = (deg_b >> 6) + 1;
+    for (int j = 0; j < nw; j++) {
+        a[j + wo] ^= b[j] << bo;
+        if (bo && j + wo + 1 < OR_PW) a[j + wo + 1] ^= b[j] >> (64 - bo);
+    }
+}
+
+/* Schoolbook remainder: cancel the leading term with a shifted copy of mu. */
+void or_poly_mod(uint64_t* a, const uint64_t* mu) {
+    int dm = or_poly_deg(mu);
+    for (int i = or_poly_deg(a); i >= dm; i--)
+        if (bit_get(a, i)) xor_shifted(a, mu, dm, i - dm);
+}
+
+/* r := a * b mod mu, shift-and-add from the top coefficient of b. */
+void or_poly_mulmod(uint64_t* r, const uint64_t* a, const uint64_t* b, const uint64_t* mu) {
+    uint64_t* ar = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    uint64_t* acc = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    memcpy(ar, a, OR_PW * sizeof(uint64_t));
+    or_poly_mod(ar, mu);
+    for (int i = or_poly_deg(b); i >= 0; i--) {
+        /* acc := acc * t mod mu */
+        for (int w = OR_PW - 1; w > 0; w--) acc[w] = (acc[w] << 1) | (acc[w - 1] >> 63);
+        acc[0] <<= 1;
+        or_poly_mod(acc, mu);
+        if (bit_get(b, i))
+            for (int w = 0; w < OR_PW; w++) acc[w] ^= ar[w];
+    }
+    memcpy(r, acc, OR_PW * sizeof(uint64_t));
+    free(ar);
+    free(acc);
+}
+
+/* Over GF(2) the cross terms of a*a cancel: a^2 = sum_i a_i t^(2i). */
+void or_poly_sqrmod(uint64_t* r, const uint64_t* a, const uint64_t* mu) {
+    uint64_t* sq = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    uint64_t* ar = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    memcpy(ar, a, OR_PW * sizeof(uint64_t));
+    or_poly_mod(ar, mu);
+    int da = or_poly_deg(ar);
+    for (int i = 0; i <= da; i++)
+        if (bit_get(ar, i)) bit_flip(sq, 2 * i);
+    or_poly_mod(sq, mu);
+    memcpy(r, sq, OR_PW * sizeof(uint64_t));
+    free(sq);
+    free(ar);
+}
+
+void or_poly_sqr_chain(uint64_t* r, const uint64_t* start, uint64_t k, const uint64_t* mu) {
+    uint64_t* cur = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    if (start) memcpy(cur, start, OR_PW * sizeof(uint64_t));
+    else cur[0] = 2; /* t */
+    or_poly_mod(cur, mu);
+    for (uint64_t s = 0; s < k; s++) or_poly_sqrmod(cur, cur, mu);
+    memcpy(r, cur, OR_PW * sizeof(uint64_t));
+    free(cur);
+}
+
+/* Left-to-right square and multiply; multiplying by t is a shift. */
+void or_poly_powmod_t(uint64_t* r, const uint64_t* e, int e_words, const uint64_t* mu) {
+    uint64_t* acc = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    acc[0] = 1;
+    or_poly_mod(acc, mu);
+    for (int i = e_words * 64 - 1; i >= 0; i--) {
+        or_poly_sqrmod(acc, acc, mu);
+        if ((e[i >> 6] >> (i & 63)) & 1u) {
+            for (int w = OR_PW - 1; w > 0; w--) acc[w] = (acc[w] << 1) | (acc[w - 1] >> 63);
+            acc[0] <<= 1;
+            or_poly_mod(acc, mu);
+        }
+    }
+    memcpy(r, acc, OR_PW * sizeof(uint64_t));
+    free(acc);
+}
+
+/* Euclid's algorithm. */
+void or_poly_gcd(uint64_t* r, const uint64_t* a, const uint64_t* b) {
+    uint64_t* x = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    uint64_t* y = (uint64_t*)calloc(OR_PW, sizeof(uint64_t));
+    memcpy(x, a, OR_PW * sizeof(uint64_t));
+    memcpy(y, b, OR_PW * sizeof(uint64_t));
+    while (or_poly_deg(y) >= 0) {
+        or_poly_mod(x, y);
+        uint64_t* t = x;
+        x = y;
+        y = t;
+    }
+    memcpy(r, x, OR_PW * sizeof(uint64_t));
+    free(x);
+    free(y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Minimal polynomial by Berlekamp-Massey (Massey 1969) over GF(2).          */
+/* The jump of Sec. 3.1 needs F^d; for the minimal polynomial mu of F,      */
+/* F^d = g(F) with g = t^d mod mu (mu(F) = 0).                              */
+/* ------------------------------------------------------------------------ */
+
+int or_minpoly(int variant, const void* canon, uint64_t* mu) {
+    const int maxdeg = 19968;                  /* nw bits: upper bound on deg mu */
+    const int N = 2 * maxdeg + 64;             /* terms of the sequence */
+    const int W = (N + 64) / 64 + 1;
+    int n = or_state_words(variant), wb = or_word_bytes(variant);
+    unsigned char* buf = (unsigned char*)malloc((size_t)n * wb);
+    memcpy(buf, canon, (size_t)n * wb);
+    int k = 0;
+    uint8_t* s = (uint8_t*)malloc(N);
+    for (int i = 0; i < N; i++) {
+        uint32_t w4[4];
+        if (variant == 0) {
+            uint32_t v;
+            or_step(0, buf, &k, &v, 1, 0);
+            s[i] = (uint8_t)(v & 1u);
+        } else if (variant == 1) {
+            uint64_t v;
+            or_step(1, buf, &k, &v, 1, 0);
+            s[i] = (uint8_t)(v & 1u);
+        } else {
+            or_step(2, buf, &k, w4, 1, 0);
+            s[i] = (uint8_t)(w4[0] & 1u);
+        }
+    }
+    /* C: connection polynomial, B: copy before the last length change,
+     * R: reversed window, bit j of R = s_{i-j}. */
+    uint64_t* C = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* B = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* T = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* R = (uint64_t*)calloc(W, sizeof(uint64_t));
+    C[0] = 1;
+    B[0] = 1;
+    int L = 0, m = 1;
+    for (int i = 0; i < N; i++) {
+        for (int w = W - 1; w > 0; w--) R[w] = (R[w] << 1) | (R[w - 1] >> 63);
+        R[0] = (R[0] << 1) | s[i];
+        /* discrepancy d = sum_{j=0..L} c_j s_{i-j} */
+        int d = 0;
+        int nwords = L / 64 + 1;
+        for (int w = 0; w < nwords; w++) d ^= __builtin_parityll(C[w] & R[w]);
+        if (d == 0) {
+            m++;
+        } else if (2 * L <= i) {
+            memcpy(T, C, W * sizeof(uint64_t));
+            int wo = m >> 6, bo = m & 63;
+            for (int w = 0; w + wo < W; w++) {
+                C[w + wo] ^= B[w] << bo;
+                if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
+            }
+            L = i + 1 - L;
+            memcpy(B, T, W * sizeof(uint64_t));
+            m = 1;
+        } else {
+            int wo = m >> 6, bo = m & 63;
+            for (int w = 0; w + wo < W; w++) {
+                C[w + wo] ^= B[w] << bo;
+                if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
+            }
+            m++;
+        }
+    }
+    /* mu(t) = t^L C(1/t): coefficient of t^j is c_{L-j}. */
+    memset(mu, 0, OR_PW * sizeof(uint64_t));
+    for (int j = 0; j <= L; j++)
+        if ((C[(L - j) >> 6] >> ((L - j) & 63)) & 1u) bit_flip(mu, j);
+    free(buf);
+    free(s);
+    free(C);
+    free(B);
+    free(T);
+    free(R);
+    return L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jump ahead, Sec. 3.1: state := g(F) state, Horner's rule from the top     */
+/* coefficient: acc := F(acc) xor g_i * X.                                   */
+/* ------------------------------------------------------------------------ */
+
+void or_jump(int variant, void* canon, const uint64_t* g) {
+    int n = or_state_words(variant), wb = or_word_bytes(variant);
+    size_t bytes = (size_t)n * wb;
+    unsigned char* acc = (unsigned char*)calloc(bytes, 1);
+    const unsigned char* X = (const unsigned char*)canon;
+    int k = 0;
+    for (int i = or_poly_deg(g); i >= 0; i--) {
+        or_step(variant, acc, &k, NULL, 1, 0);
+        if (bit_get(g, i)) {
+            for (int j = 0; j < n; j++) {
+                unsigned char* dst = acc + (size_t)((k + j) % n) * wb;
+                const unsigned char* src = X + (size_t)j * wb;
+                for (int b = 0; b < wb; b++) dst[b] ^= src[b];
+            }
+        }
+    }
+    or_canon(variant, acc, k, canon);
+    free(acc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The V-stream, Sec. 3 eq. (combseq): lane t starts t*J steps into the      */
+/* base sequence, lanes are polled round robin.                              */
+/* ------------------------------------------------------------------------ */
+
+struct or_vgen {
+    int variant, M, n, wb;
+    uint64_t pos;       /* stream elements emitted (uint32 units for SFMT) */
+    unsigned char* buf; /* M circular buffers */
+    int* k;             /* oldest slot per lane */
+    uint32_t* cur;      /* SFMT: newest 128-bit word per lane */
+};
+
+or_vgen* or_vgen_new(int variant, int M, const void* canon0, const uint64_t* gJ) {
+    or_vgen* v = (or_vgen*)calloc(1, sizeof(or_vgen));
+    v->variant = variant;
+    v->M = M;
+    v->n = or_state_words(variant);
+    v->wb = or_word_bytes(variant);
+    size_t bytes = (size_t)v->n * v->wb;
+    v->buf = (unsigned char*)malloc(bytes * M);
+    v->k = (int*)calloc(M, sizeof(int));
+    v->cur = (uint32_t*)calloc((size_t)4 * M, sizeof(uint32_t));
+    memcpy(v->buf, canon0, bytes);
+    for (int t = 1; t < M; t++) {
+        memcpy(v->buf + bytes * t, v->buf + bytes * (t - 1), bytes);
+        or_jump(variant, v->buf + bytes * t, gJ);
+    }
+    return v;
+}
+
+void or_vgen_free(or_vgen* v) {
+    if (!v) return;
+    free(v->buf);
+    free(v->k);
+    free(v->cur);
+    free(v);
+}
+
+void or_vgen_generate(or_vgen* v, void* out, size_t count) {
+    size_t bytes = (size_t)v->n * v->wb;
+    for (size_t i = 0; i < count; i++) {
+        if (v->variant == 0) {
+            int t = (int)(v->pos % (uint64_t)v->M);
+            or_step(0, v->buf + bytes * t, &v->k[t], (uint32_t*)out + i, 1, 1);
+        } else if (v->variant == 1) {
+            int t = (int)(v->pos % (uint64_t)v->M);
+            or_step(1, v->buf + bytes * t, &v->k[t], (uint64_t*)out + i, 1, 1);
+        } else {
+            uint64_t e = v->pos / 4;
+            int j = (int)(v->pos % 4);
+            int t = (int)(e % (uint64_t)v->M);
+            if (j == 0) or_step(2, v->buf + bytes * t, &v->k[t], v->cur + 4 * t, 1, 0);
+            ((uint32_t*)out)[i] = v->cur[4 * t + j];
+        }
+        v->pos++;
+    }
+}
+
+void or_vgen_jump(or_vgen* v, const uint64_t* g) {
+    size_t bytes = (size_t)v->n * v->wb;
+    unsigned char* canon = (unsigned char*)malloc(bytes);
+    for (int t = 0; t < v->M; t++) {
+        or_canon(v->variant, v->buf + bytes * t, v->k[t], canon);
+        or_jump(v->variant, canon, g);
+        memcpy(v->buf + bytes * t, canon, bytes);
+        v->k[t] = 0;
+        /* the newest word of the jumped lane is its pending 128-bit word */
+        if (v->variant == 2) memcpy(v->cur + 4 * t, canon + bytes - 16, 16);
+    }
+    free(canon);
+}
+
+uint64_t or_vgen_pos(const or_vgen* v) { return v->pos; }
+
+void or_vgen_lane_canon(const or_vgen* v, int t, void* canon) {
+    size_t bytes = (size_t)v->n * v->wb;
+    or_canon(v->variant, v->buf + bytes * t, v->k[t], canon);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed integer-to-float maps: keep the top bits that fit the mantissa and  */
+/* scale by a power of two; every result is exact.                           */
+/* ------------------------------------------------------------------------ */
+
+float or_u32_to_f32(uint32_t u) { return (float)((double)(u >> 8) * 0x1p-24); }
+double or_u64_to_f64(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+float or_u64_to_f32(uint64_t u) { return (float)((double)(u >> 40) * 0x1p-24); }
+double or_u32pair_to_f64(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * 0x1p-53;
+}
+void or_map_f32(const uint32_t* u, float* f, size_t n) {
+    for (size_t i = 0; i < n; i++) f[i] = or_u32_to_f32(u[i]);
+}
+void or_map_f64(const uint64_t* u, double* f, size_t n) {
+    for (size_t i = 0; i < n; i++) f[i] = or_u64_to_f64(u[i]);
+}

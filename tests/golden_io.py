@@ -1,0 +1,36 @@
+"""Readers for the fixtures under tests/golden/ (written by make_golden.py)."""
+import functools
+import os
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NAMES = {0: "mt32", 1: "mt64", 2: "sfmt"}
+
+
+@functools.lru_cache(maxsize=None)
+def minpoly(variant: int) -> int:
+    with open(os.path.join(GOLDEN, f"minpoly_{NAMES[variant]}.txt")) as f:
+        for line in f:
+            if line.startswith("mu "):
+                return int(line.split()[1], 16)
+    raise ValueError("no mu line")
+
+
+@functools.lru_cache(maxsize=None)
+def tpow2(variant: int) -> dict:
+    """{q: t^(2^q) mod mu} for q = 19931..19937."""
+    out = {}
+    with open(os.path.join(GOLDEN, f"tpow2_{NAMES[variant]}.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v = line.split()
+            out[int(k)] = int(v, 16)
+    return out
+
+
+def lane_poly(variant: int, M: int) -> int:
+    """t^J mod mu with J = 2^(19937 - log2 M), Sec. 3 (Table jvalues)."""
+    if M == 1:
+        return 1
+    q = 19937 - (M.bit_length() - 1)
+    return tpow2(variant)[q]

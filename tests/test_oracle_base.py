@@ -1,0 +1,182 @@
+"""Pins of the oracle's base generators (Sec. 2 of the paper) against things
+other than the oracle: the C++ standard library engines, numpy and CPython
+seeding, and algebraic structure for SFMT19937."""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from tests import stdpins
+
+
+# ---- MT19937-32 / MT19937-64: eq. (step), (matmult), (tempering), (params), (params64)
+
+
+def test_mt32_default_seed_matches_cpp_standard():
+    out = O.Scalar(O.MT32, O.seed_state(O.MT32, 5489)).out(10000)
+    assert int(out[9999]) == 4123659995  # C++ [rand.predef] mt19937
+    np.testing.assert_array_equal(out, stdpins.std_stream(32, 5489, 10000))
+
+
+def test_mt64_default_seed_matches_cpp_standard():
+    out = O.Scalar(O.MT64, O.seed_state(O.MT64, 5489)).out(10000)
+    assert int(out[9999]) == 9981545732273789042  # C++ [rand.predef] mt19937_64
+    np.testing.assert_array_equal(out, stdpins.std_stream(64, 5489, 10000))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 42, 0xFFFFFFFF, 123456789])
+def test_mt32_other_seeds_match_std(seed):
+    out = O.Scalar(O.MT32, O.seed_state(O.MT32, seed)).out(2000)
+    np.testing.assert_array_equal(out, stdpins.std_stream(32, seed, 2000))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 42, 2**64 - 1, 0x123456789ABCDEF])
+def test_mt64_other_seeds_match_std(seed):
+    out = O.Scalar(O.MT64, O.seed_state(O.MT64, seed)).out(2000)
+    np.testing.assert_array_equal(out, stdpins.std_stream(64, seed, 2000))
+
+
+@pytest.mark.parametrize("seed", [5489, 7, 2**31 + 5])
+def test_mt32_init_genrand_matches_numpy(seed):
+    key = np.random.RandomState(seed).get_state()[1]
+    np.testing.assert_array_equal(O.seed_state(O.MT32, seed), key)
+
+
+@pytest.mark.parametrize(
+    "key", [[0x123, 0x234, 0x345, 0x456], [1, 2], list(range(1, 700)), [0xFFFFFFFF, 0, 7, 2**31]]
+)
+def test_mt32_init_by_array_matches_numpy(key):
+    # (numpy squeezes a one-element seed array to a scalar seed, so keys here
+    # have two or more words; CPython covers one-word keys below)
+    ref = np.random.RandomState(np.array(key, dtype=np.uint32)).get_state()[1]
+    np.testing.assert_array_equal(O.seed_state(O.MT32, key=key), ref)
+
+
+def test_mt32_init_by_array_matches_cpython_random():
+    # random.seed(int) seeds MT19937 by init_by_array over the int's 32-bit chunks
+    for seed in (12345, 2**40 + 17):
+        r = random.Random(seed)
+        words = []
+        v = seed
+        while v:
+            words.append(v & 0xFFFFFFFF)
+            v >>= 32
+        state = np.array(r.getstate()[1][:624], dtype=np.uint32)
+        np.testing.assert_array_equal(O.seed_state(O.MT32, key=words), state)
+        out = O.Scalar(O.MT32, O.seed_state(O.MT32, key=words)).out(100)
+        assert [int(v) for v in out] == [r.getrandbits(32) for _ in range(100)]
+
+
+def test_res53_double_map_matches_numpy():
+    # numpy random_sample: two consecutive MT19937 outputs a, b -> ((a>>5) 2^26 + (b>>6)) 2^-53
+    rs = np.random.RandomState(99)
+    ref = rs.random_sample(50)
+    u = O.Scalar(O.MT32, O.seed_state(O.MT32, 99)).out(100)
+    got = [O.u32pair_to_f64(int(u[2 * i]), int(u[2 * i + 1])) for i in range(50)]
+    assert got == list(ref)
+
+
+def test_tempering_is_invertible_on_samples():
+    # g is a bijection of w-bit words (each step is an invertible xorshift);
+    # distinct inputs must give distinct outputs
+    xs = np.arange(0, 1 << 20, dtype=np.uint32)
+    ys = {O.lib().or_mt32_temper(int(v)) for v in xs[:: 1 << 6]}
+    assert len(ys) == len(xs[:: 1 << 6])
+
+
+# ---- SFMT19937: eq. (sfmt_step), (sfmt_params)
+
+
+def _sfmt_step_bigint(state_words):
+    """Independent formulation of eq. (sfmt_step) with Python integers as the
+    128-bit words (sub-word 0 least significant)."""
+    W = [sum(int(state_words[4 * k + j]) << (32 * j) for j in range(4)) for k in range(156)]
+    K = (0xDFFFFFEF, 0xDDFECB7F, 0xBFFAFFFF, 0xBFFFFFF6)
+    mask128 = (1 << 128) - 1
+
+    def per_sub(v, f):
+        return sum((f(j, (v >> (32 * j)) & 0xFFFFFFFF) & 0xFFFFFFFF) << (32 * j) for j in range(4))
+
+    out = []
+    for k in range(400):
+        a, b, c, d = W[k], W[k + 122], W[k + 154], W[k + 155]
+        r = a ^ ((a << 8) & mask128) ^ per_sub(b, lambda j, s: (s >> 11) & K[j]) ^ (c >> 8)
+        r ^= per_sub(d, lambda j, s: s << 18)
+        W.append(r)
+        out.append(r)
+    return out
+
+
+def test_sfmt_step_two_formulations_agree():
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 2**32, 624, dtype=np.uint64).astype(np.uint32)
+    got = O.Scalar(O.SFMT, x).out(400)
+    ref = _sfmt_step_bigint(x)
+    for k in range(400):
+        assert sum(int(got[k][j]) << (32 * j) for j in range(4)) == ref[k]
+
+
+def test_sfmt_minpoly_has_one_irreducible_factor_of_degree_19937(golden):
+    # Structural pin of the 128-bit word order and shifts: the period claim of
+    # Sec. 2.4 needs an irreducible degree-19937 factor in the minimal
+    # polynomial. gcd(mu, t^(2^19937) - t) collects the distinct irreducible
+    # factors of degree 1 or 19937; mu(0) = mu(1) = 1 rules out degree 1.
+    mu = golden.minpoly(O.SFMT)
+    assert mu.bit_length() - 1 == 19968
+    assert mu & 1 == 1 and bin(mu).count("1") % 2 == 1
+    g = O.poly_gcd(mu, golden.tpow2(O.SFMT)[19937] ^ 2)
+    assert g.bit_length() - 1 == 19937
+
+
+def _parity(x, vec):
+    v = 0
+    for j in range(4):
+        v ^= int(x[j]) & vec[j]
+    return bin(v).count("1") & 1
+
+
+def test_sfmt_parity_vector_annihilates_psi_component(golden):
+    # Period certification must leave the state outside V_psi = ker psi(F),
+    # the part outside the degree-19937 factor phi. It can only do that if
+    # <PARITY, word 0> vanishes on V_psi, which is the image of phi(F).
+    mu = golden.minpoly(O.SFMT)
+    phi = O.poly_gcd(mu, golden.tpow2(O.SFMT)[19937] ^ 2)
+    parity = (1, 0, 0, 0x13C9E684)
+    wrong = (1, 0, 0, 0x13C9E686)
+    rng = np.random.default_rng(11)
+    wrong_hits = 0
+    for _ in range(12):
+        x = rng.integers(0, 2**32, 624, dtype=np.uint64).astype(np.uint32)
+        y = O.jump_canon(O.SFMT, x, phi)
+        assert _parity(y, parity) == 0
+        wrong_hits += _parity(y, wrong)
+    assert wrong_hits > 0
+
+
+@pytest.mark.parametrize("seed", [1234, 4321, 0, 1, 99991])
+def test_sfmt_certified_state_has_odd_parity(seed):
+    x = O.seed_state(O.SFMT, seed)
+    assert _parity(x, (1, 0, 0, 0x13C9E684)) == 1
+
+
+def test_sfmt_seed_1234_certification_flips():
+    # recorded reading: for seed 1234 the certification fires (bit 0 of w_0)
+    assert O.sfmt_certification_flipped(1234)
+
+
+# ---- fixed integer-to-float maps
+
+
+def test_float_maps_are_exact_and_in_range():
+    u32 = np.array([0, 1, 255, 256, 0x80000000, 0xFFFFFFFF], dtype=np.uint32)
+    f = O.map_f32(u32)
+    assert list(f) == [0.0, 0.0, 0.0, 2.0**-24, 0.5, 1.0 - 2.0**-24]
+    u64 = np.array([0, 2047, 2048, 1 << 63, 2**64 - 1], dtype=np.uint64)
+    d = O.map_f64(u64)
+    assert list(d) == [0.0, 0.0, 2.0**-53, 0.5, 1.0 - 2.0**-53]
+    assert O.u64_to_f32(2**64 - 1) == 1.0 - 2.0**-24
+    rng = np.random.default_rng(0)
+    u = rng.integers(0, 2**32, 10000, dtype=np.uint64).astype(np.uint32)
+    f = O.map_f32(u).astype(np.float64)
+    np.testing.assert_array_equal(f * 2.0**24, (u >> 8).astype(np.float64))
