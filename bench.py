@@ -1,0 +1,310 @@
+"""Benchmark: batched V-MT19937-32 generation on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (one step): 65,536 independent V-MT19937-32 generators (M = 16
+lanes), seeded by init_by_array with 4-word keys from splitmix64(42), each
+asked for a log-uniform number of uint32 in [1e3, 1e7) (splitmix64(43)):
+about 287 GB of output per step. States stay resident in HBM; each step
+continues every stream. The output of a step is larger than HBM, so it is
+written in rounds into an output arena (every round's tasks get disjoint
+slices; the next round overwrites the arena, as a consumer that drains each
+round would). One round = one persistent-kernel launch over its tasks,
+longest first.
+
+Printed: ONE JSON line with the output GB/s of the step (value), the
+roofline of the persistent kernel (HIP events on its stream), the plain form
+(one launch per generator, same kernel), single-stream rates of the other
+configurations, lane de-phasing (init) cost, and the oracle's rate on the
+host as cpu_baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "output GB/s vs HBM-write roofline, batched vs plain; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+N_GEN = 65536
+M_LANES = 16
+STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--generators", type=int, default=N_GEN)
+    ap.add_argument("--arena-gib", type=float, default=96.0)
+    ap.add_argument("--plain-sample", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--skip-secondary", action="store_true")
+    ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
+    return ap.parse_args()
+
+
+def plan_rounds(lens: np.ndarray, arena_bytes: int, elem_bytes: int):
+    """Deal the tasks (longest first) round-robin over R rounds and give each
+    task a 256-byte aligned slice of the arena within its round."""
+    total = int(sum(((int(n) * elem_bytes + 255) // 256) * 256 for n in lens))
+    R = max(1, -(-total // arena_bytes))
+    while True:
+        order = np.argsort(-lens.astype(np.int64), kind="stable")
+        rounds = [order[r::R] for r in range(R)]
+        offs = {}
+        ok = True
+        for r, idx in enumerate(rounds):
+            off = 0
+            for i in idx:
+                offs[int(i)] = off
+                off += ((int(lens[i]) * elem_bytes + 255) // 256) * 256
+            if off > arena_bytes:
+                ok = False
+                break
+        if ok:
+            return rounds, offs
+        R += 1
+
+
+def cpu_baseline(seconds: float) -> dict:
+    """The oracle, as it is, on the host: a few V-MT19937-32 (M = 16) streams
+    keyed like the batch serve the batch's request lengths in order."""
+    from oracle import pyoracle as O
+    from paper_2309_16682_amd.workload import batch_keys, batch_lengths
+    from tests import golden_io
+
+    keys = batch_keys(4, seed=42)
+    lens = batch_lengths(N_GEN, seed=43)
+    gJ = golden_io.lane_poly(0, M_LANES)
+    streams = [O.VStream(0, M_LANES, O.seed_state(0, key=k), gJ) for k in keys]
+    done = 0
+    i = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        streams[i % len(streams)].generate(int(lens[i]))
+        done += int(lens[i])
+        i += 1
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(done * 4 / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"oracle V-MT19937-32 (M=16), 4 init_by_array generators serving the first {i} request "
+        f"lengths of the batch workload: {done} uint32 in {dt:.1f} s on one host thread "
+        f"({os.cpu_count()} host CPUs)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(
+            f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+            "(independent generators shard across GPUs with no communication)",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+
+    import torch
+
+    from paper_2309_16682_amd import vmt
+    from paper_2309_16682_amd.workload import batch_keys, batch_lengths
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    ctx = vmt.vmt_ctx_create(0)
+
+    G = args.generators
+    keys = batch_keys(G, seed=42)
+    lens = batch_lengths(G, seed=43)
+    sb = vmt.vmt_state_bytes(vmt.VMT_MT32, M_LANES)
+    state_pool = torch.empty(G * sb, dtype=torch.uint8, device=dev)
+    states = [state_pool[i * sb : (i + 1) * sb] for i in range(G)]
+
+    # ---- lane de-phasing: seeding + M-1 jump-aheads per generator (device)
+    t0 = time.perf_counter()
+    vmt.vmt_ctx_create  # noqa: B018 (context already holds the lane tables after first use)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    vmt.vmt_init_by_array(ctx, vmt.VMT_MT32, keys[0], M_LANES, states[0])  # builds the lane table
+    torch.cuda.synchronize()
+    host_poly_s = time.perf_counter() - t0
+    e0.record()
+    vmt.vmt_init_by_array_batch(ctx, keys, M_LANES, states)
+    e1.record()
+    torch.cuda.synchronize()
+    init_ms = e0.elapsed_time(e1)
+    log(f"init: {G} generators in {init_ms:.1f} ms (+{host_poly_s:.2f} s host polynomials)")
+
+    # ---- arena and rounds
+    free, _ = torch.cuda.mem_get_info()
+    arena_bytes = int(min(args.arena_gib * 2**30, free - 16 * 2**30))
+    arena_bytes = max(arena_bytes, 1 << 30)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    rounds, offs = plan_rounds(lens, arena_bytes, 4)
+    base = arena.data_ptr()
+    plans = []
+    round_alg_bytes = []
+    for idx in rounds:
+        sp = [states[int(i)].data_ptr() for i in idx]
+        ln = [int(lens[i]) for i in idx]
+        op = [base + offs[int(i)] for i in idx]
+        plans.append(vmt.vmt_batch_plan_create(ctx, sp, ln, op, vmt.VMT_OUT_U32))
+        round_alg_bytes.append(sum(ln) * 4 + len(idx) * 2 * STATE_WIN_BYTES)
+    step_out_bytes = int(lens.sum()) * 4
+    log(f"rounds: {len(plans)} over a {arena_bytes / 2**30:.1f} GiB arena; {step_out_bytes / 1e9:.1f} GB per step")
+
+    def step(evs=None):
+        for r, p in enumerate(plans):
+            if evs is not None:
+                evs[r][0].record()
+            vmt.vmt_batch_plan_launch(p)
+            if evs is not None:
+                evs[r][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs_all = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in plans]
+        step(evs)
+        evs_all.append(evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    launch_ms = [[a.elapsed_time(b) for a, b in evs] for evs in evs_all]
+    kern_ms_total = float(np.sum(launch_ms))
+    alg_total = sum(round_alg_bytes) * args.steps
+    achieved = alg_total / (kern_ms_total * 1e-3) / 1e9
+    value = step_out_bytes / (ms_per_step * 1e-3) / 1e9
+    log(f"batched: {ms_per_step:.2f} ms/step, {value:.1f} GB/s output; kernel avg {np.mean(launch_ms):.3f} ms/launch")
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched V-MT19937-32, M=16 lanes, {G} generators (init_by_array keys from "
+            f"splitmix64(42)), log-uniform request lengths in [1e3,1e7) uint32 (splitmix64(43)), "
+            f"persistent kernel, longest first",
+            "generators": G,
+            "lanes": M_LANES,
+            "elements_per_step": int(lens.sum()),
+            "output_bytes_per_step": step_out_bytes,
+            "rounds": len(plans),
+            "arena_gib": round(arena_bytes / 2**30, 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "batch_mt_kernel<MT32, 16 lanes, u32>",
+            "avg_launch_ms": round(float(np.mean(launch_ms)), 4),
+            "alg_bytes_per_launch": int(np.mean(round_alg_bytes)),
+        },
+        "init": {"generators": G, "device_ms": round(init_ms, 2), "lane_jumps": G * (M_LANES - 1),
+                 "host_poly_s": round(host_poly_s, 3)},
+    }
+    if args.only_batch:
+        print(json.dumps(result), flush=True)
+        return
+
+    # ---- plain form: one launch per generator (same kernel family), sample
+    rng = np.random.default_rng(5)
+    sample = rng.choice(G, size=min(args.plain_sample, G), replace=False)
+    out_base = arena
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    off = 0
+    plain_bytes = 0
+    for i in sample:
+        n = int(lens[i])
+        view = out_base[off : off + n * 4]
+        vmt.vmt_generate_u32(ctx, states[int(i)], n, view)
+        off += ((n * 4 + 255) // 256) * 256
+        plain_bytes += n * 4
+    e1.record()
+    torch.cuda.synchronize()
+    plain_s = e0.elapsed_time(e1) * 1e-3
+    result["plain"] = {
+        "value": round(plain_bytes / plain_s / 1e9, 3),
+        "unit": "GB/s",
+        "form": "one vmt_generate_u32 launch per generator, same stream",
+        "sample": f"{len(sample)} random generators of the batch, {plain_bytes / 1e9:.2f} GB",
+        "speedup_batched_vs_plain": round(value / (plain_bytes / plain_s / 1e9), 1),
+    }
+    log(f"plain: {result['plain']['value']} GB/s")
+
+    # ---- single-stream configurations (one generator each)
+    if not args.skip_secondary:
+        sec = {}
+        del arena
+        torch.cuda.empty_cache()
+        for name, variant, M, seed, n, kind in (
+            ("mt32_M16_2^24_u32", vmt.VMT_MT32, 16, 5489, 1 << 24, "u32"),
+            ("mt64_M8_2^26_u64", vmt.VMT_MT64, 8, 5489, 1 << 26, "u64"),
+            ("mt64_M8_2^26_f64", vmt.VMT_MT64, 8, 5489, 1 << 26, "f64"),
+            ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, "u32"),
+            ("sfmt_M64_2^28_u32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "u32"),
+            ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
+        ):
+            st = vmt.new_state(variant, M)
+            vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+            esz = 8 if kind in ("u64", "f64") else 4
+            out = torch.empty(n * esz, dtype=torch.uint8, device=dev)
+            fn = {"u32": vmt.vmt_generate_u32, "u64": vmt.vmt_generate_u64, "f64": vmt.vmt_uniform_f64,
+                  "f32": vmt.vmt_uniform_f32}[kind]
+            fn(ctx, st, n, out)
+            torch.cuda.synchronize()
+            reps = 2 if variant == vmt.VMT_SFMT and M == 4 else 3
+            e0.record()
+            for _ in range(reps):
+                fn(ctx, st, n, out)
+            e1.record()
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) * 1e-3 / reps
+            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3)}
+            log(f"{name}: {sec[name]}")
+            del out
+        result["single_stream"] = sec
+
+    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    log(f"cpu baseline: {result['cpu_baseline']['value']} GB/s")
+    for p in plans:
+        vmt.vmt_batch_plan_destroy(p)
+    vmt.vmt_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * vmt.h -- C ABI of libvmt: V-family Mersenne Twister generators on MI355X.
+ *
+ * Implements the generators of F. Cannizzo, "VMT19937: A SIMD-Friendly Pseudo
+ * Random Number Generator based on Mersenne Twister 19937" (arXiv 2309.16682):
+ * M copies of a base generator (MT19937-32, MT19937-64 or SFMT19937), copy t
+ * started t*J steps into the base sequence by jump-ahead, polled round robin
+ * into one stream (Sec. 3, eq. combseq; J = 2^(19937 - log2 M), Table jvalues).
+ *
+ * Conventions for every call
+ *   - Status: every function returning int returns VMT_OK (0) or a negative
+ *     VMT_E* code. Nothing aborts and no exception crosses the ABI. The
+ *     message for the last failure on the calling thread is vmt_last_error().
+ *   - Memory: the caller owns state and output buffers (device memory, e.g.
+ *     torch tensors). The context owns only its polynomial tables and the
+ *     registry that records the variant and lane count of each state it has
+ *     initialised or imported. A state must be initialised (vmt_init_*) or
+ *     imported (vmt_state_import) through a context before other calls use it.
+ *   - Streams: device work is enqueued on the caller's hipStream_t (NULL =
+ *     the null stream) and is stream-ordered; results are valid once the
+ *     stream has reached the call. Calls return before the GPU work ends.
+ *   - Failure: arguments are checked on the host before anything is
+ *     enqueued; a call that returns an error has enqueued nothing and left the
+ *     state unchanged.
+ *   - Concurrency: calls on different states may overlap on different
+ *     streams. Calls on one state must be ordered by the caller (one stream).
+ *
+ * Stream elements. MT19937-32: uint32. MT19937-64: uint64. SFMT19937: the
+ * uint32 sub-words of its 128-bit words (sub-word 0 first), the round robin
+ * over lanes taken per 128-bit word.
+ */
+#ifndef VMT_H
+#define VMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VMT_OK 0
+#define VMT_EINVAL (-1)   /* bad argument: NULL pointer, unsupported M, size  */
+#define VMT_EVARIANT (-2) /* operation not defined for this generator variant */
+#define VMT_ENOMEM (-3)   /* host or device allocation failed                 */
+#define VMT_EDEVICE (-4)  /* HIP runtime error                                 */
+#define VMT_EBUSY (-5)    /* resource in use                                   */
+#define VMT_ESTATE (-6)   /* state not registered or header inconsistent      */
+
+/* generator variants (Sec. 2.2, 2.3, 2.4) */
+#define VMT_MT32 0
+#define VMT_MT64 1
+#define VMT_SFMT 2
+
+/* output kinds for vmt_batch_generate */
+#define VMT_OUT_U32 0
+#define VMT_OUT_U64 1
+#define VMT_OUT_F32 2
+#define VMT_OUT_F64 3
+
+typedef struct vmt_ctx vmt_ctx;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* vmt_last_error(void);
+
+/* Library version string. */
+const char* vmt_version(void);
+
+/* Create a context on HIP device `device`. On failure returns NULL and, if
+ * status is not NULL, stores the error code there. The context computes the
+ * minimal polynomials of the three base generators and the lane polynomials
+ * it needs lazily, on the host, and keeps them for its lifetime. */
+vmt_ctx* vmt_ctx_create(int device, int* status);
+
+/* Destroy a context: frees its device tables. Waits for the device. */
+int vmt_ctx_destroy(vmt_ctx* ctx);
+
+/* Bytes of device memory a state of `variant` with M lanes occupies: a
+ * 256-byte header plus the lane-interleaved window, n words x M lanes
+ * (word k of lane t at index k*M + t). M must be a power of two in [1, 64].
+ * Returns 0 for an invalid variant or M. */
+size_t vmt_state_bytes(int variant, uint32_t M);
+
+/* Initialise a V-state (Sec. 3, Sec. 3.1). The base state X_0 comes from
+ * `seed` by the base generator's published init_genrand rule (the paper
+ * leaves seeding open): MT19937-32 and SFMT19937 take the low 32 bits of
+ * seed, SFMT then applies its period certification. Lane t becomes X_0
+ * advanced by t*J steps, J = 2^(19937 - log2 M). The first element of the
+ * stream is the base generator's first output. d_state must hold
+ * vmt_state_bytes(variant, M) bytes of device memory, 256-byte aligned. */
+int vmt_init_genrand(vmt_ctx* ctx, int variant, uint64_t seed, uint32_t M, void* d_state,
+                     hipStream_t stream);
+
+/* As vmt_init_genrand, with X_0 from init_by_array(key[0..key_len-1]) of the
+ * MT19937 release (host array). MT19937-32 only (VMT_EVARIANT otherwise);
+ * 1 <= key_len <= 4096. */
+int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key_len, uint32_t M,
+                      void* d_state, hipStream_t stream);
+
+/* Batched vmt_init_by_array: count states, state i keyed by
+ * keys[i*key_len .. i*key_len + key_len - 1] (host array), all MT19937-32
+ * with M lanes; d_states is a host array of count device pointers. */
+int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, size_t count,
+                            uint32_t M, void* const* d_states, hipStream_t stream);
+
+/* Jump ahead (Sec. 3.1): every lane advances d base steps, i.e. the stream
+ * skips d*M elements (4*d*M uint32 for SFMT19937). d is the little-endian
+ * multiword integer dist_le[0..dist_words-1] (host array; dist_words <= 320).
+ * The jump polynomial t^d mod (minimal polynomial) is computed on the host
+ * and cached per distance; the state is updated on the device. */
+int vmt_jump(vmt_ctx* ctx, void* d_state, const uint64_t* dist_le, size_t dist_words,
+             hipStream_t stream);
+
+/* vmt_jump with d = 2^k, k <= 65536. */
+int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream);
+
+/* Batched jump by 2^k: count states (host array of device pointers), state i
+ * jumped by 2^ks[i]; all states must share variant and M. */
+int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count,
+                        hipStream_t stream);
+
+/* Next n stream elements into d_out (device). generate_u32: MT19937-32 and
+ * SFMT19937. generate_u64: MT19937-64. n may be 0. */
+int vmt_generate_u32(vmt_ctx* ctx, void* d_state, size_t n, uint32_t* d_out, hipStream_t stream);
+int vmt_generate_u64(vmt_ctx* ctx, void* d_state, size_t n, uint64_t* d_out, hipStream_t stream);
+
+/* Uniform floats in [0, 1) by fixed exact maps of the stream elements, one
+ * element per output: f32 = (u32 >> 8) * 2^-24 for MT19937-32 and SFMT19937,
+ * (u64 >> 40) * 2^-24 for MT19937-64; f64 = (u64 >> 11) * 2^-53 for
+ * MT19937-64 (VMT_EVARIANT for the 32-bit generators). */
+int vmt_uniform_f32(vmt_ctx* ctx, void* d_state, size_t n, float* d_out, hipStream_t stream);
+int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStream_t stream);
+
+/* Batched generation: state i writes lens[i] elements of kind out_kind into
+ * d_outs[i]. d_states, lens and d_outs are host arrays of count entries; all
+ * states must share variant and M. One persistent kernel processes the
+ * states longest first from a device work queue. Each state must appear at
+ * most once per call. */
+int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
+                       size_t count, int out_kind, hipStream_t stream);
+
+/* Plan form of vmt_batch_generate for repeated replay: uploads the task list
+ * once and returns a handle whose launch reuses it (the same states, lengths
+ * and outputs each time; states advance on every launch). The launch can be
+ * captured into a HIP graph by the caller. */
+typedef struct vmt_batch_plan vmt_batch_plan;
+vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens,
+                                      void* const* d_outs, size_t count, int out_kind, int* status);
+int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream);
+int vmt_batch_plan_destroy(vmt_batch_plan* plan);
+
+/* Copy a state to or from host memory (bytes = vmt_state_bytes). Import
+ * validates the header and registers the state with the context. Both
+ * synchronise `stream`. */
+int vmt_state_export(vmt_ctx* ctx, const void* d_state, void* h_buf, size_t bytes, hipStream_t stream);
+int vmt_state_import(vmt_ctx* ctx, void* d_state, const void* h_buf, size_t bytes, hipStream_t stream);
+
+/* Forget a state: the context's registry is keyed by device address, so a
+ * caller that frees a state's memory should release it first (a later
+ * allocation at the same address must be initialised or imported again). */
+int vmt_state_release(vmt_ctx* ctx, const void* d_state);
+
+/* Host helpers (no device work). Minimal polynomial of the one-step map of a
+ * base generator and t^d mod it, as little-endian bit arrays (bit i of the
+ * uint64 array = coefficient of t^i); cap = words available in out. */
+int vmt_minpoly(vmt_ctx* ctx, int variant, uint64_t* out, size_t cap, int* degree);
+int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dist_words, uint64_t* out,
+                  size_t cap, int* degree);
+
+/* Launch-shape override for tests and the autotuner: lanes per workgroup
+ * (0 = automatic) for single-state generation. */
+int vmt_set_tuning(vmt_ctx* ctx, int variant, uint32_t lanes_per_wg, uint32_t threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,307 @@
+// gf2poly.cpp -- host GF(2)[t] arithmetic for the jump-ahead (Sec. 3.1).
+#include "gf2poly.hpp"
+
+#include <immintrin.h>
+
+#include <algorithm>
+#include <cstring>
+#include <stdexcept>
+
+namespace vmt {
+
+int poly_degree(const Words& a) {
+    for (size_t i = a.size(); i-- > 0;)
+        if (a[i]) return int(i * 64 + 63 - __builtin_clzll(a[i]));
+    return -1;
+}
+
+void poly_trim(Words& a) {
+    while (!a.empty() && a.back() == 0) a.pop_back();
+}
+
+// ---- carry-less multiplication -------------------------------------------
+
+// r[0..2n) = a[0..n) * b[0..n), schoolbook on 64x64 -> 128 carry-less products.
+static void mul_base(const uint64_t* a, const uint64_t* b, size_t n, uint64_t* r) {
+    std::memset(r, 0, 2 * n * sizeof(uint64_t));
+    for (size_t i = 0; i < n; i++) {
+        if (!a[i]) continue;
+        const __m128i ai = _mm_cvtsi64_si128((long long)a[i]);
+        __m128i carry = _mm_setzero_si128();
+        for (size_t j = 0; j < n; j++) {
+            __m128i p = _mm_clmulepi64_si128(ai, _mm_cvtsi64_si128((long long)b[j]), 0x00);
+            p = _mm_xor_si128(p, carry);
+            r[i + j] ^= (uint64_t)_mm_cvtsi128_si64(p);
+            carry = _mm_srli_si128(p, 8);
+        }
+        r[i + n] ^= (uint64_t)_mm_cvtsi128_si64(carry);
+    }
+}
+
+// Karatsuba over word halves; tmp needs 8n + 64 words.
+static void mul_kara(const uint64_t* a, const uint64_t* b, size_t n, uint64_t* r, uint64_t* tmp) {
+    if (n <= 20) {
+        mul_base(a, b, n, r);
+        return;
+    }
+    const size_t h = n / 2, hh = n - h;  // low h words, high hh >= h words
+    mul_kara(a, b, h, r, tmp);                   // a0 b0 -> r[0, 2h)
+    mul_kara(a + h, b + h, hh, r + 2 * h, tmp);  // a1 b1 -> r[2h, 2n)
+    uint64_t* sa = tmp;
+    uint64_t* sb = tmp + hh;
+    uint64_t* mid = tmp + 2 * hh;
+    uint64_t* rest = tmp + 4 * hh;
+    for (size_t i = 0; i < hh; i++) {
+        sa[i] = (i < h ? a[i] : 0) ^ a[h + i];
+        sb[i] = (i < h ? b[i] : 0) ^ b[h + i];
+    }
+    mul_kara(sa, sb, hh, mid, rest);  // (a0+a1)(b0+b1)
+    for (size_t i = 0; i < 2 * h; i++) mid[i] ^= r[i];
+    for (size_t i = 0; i < 2 * hh; i++) mid[i] ^= r[2 * h + i];
+    for (size_t i = 0; i < 2 * hh; i++) r[h + i] ^= mid[i];
+}
+
+Words poly_mul(const Words& a, const Words& b) {
+    const size_t n = std::max(a.size(), b.size());
+    if (n == 0) return {};
+    Words pa(a), pb(b);
+    pa.resize(n, 0);
+    pb.resize(n, 0);
+    Words r(2 * n, 0), tmp(8 * n + 64, 0);
+    mul_kara(pa.data(), pb.data(), n, r.data(), tmp.data());
+    return r;
+}
+
+// ---- shifts -----------------------------------------------------------------
+
+static Words shr_bits(const Words& a, int s) {  // floor(a / t^s)
+    const size_t wo = size_t(s) / 64;
+    const int bo = s % 64;
+    if (wo >= a.size()) return {};
+    Words r(a.size() - wo, 0);
+    for (size_t i = 0; i < r.size(); i++) {
+        uint64_t lo = a[i + wo] >> bo;
+        uint64_t hi = (bo && i + wo + 1 < a.size()) ? a[i + wo + 1] << (64 - bo) : 0;
+        r[i] = lo | hi;
+    }
+    return r;
+}
+
+// ---- arithmetic modulo mu ---------------------------------------------------
+
+PolyMod::PolyMod(const Words& mu) : mu_(mu) {
+    poly_trim(mu_);
+    D_ = poly_degree(mu_);
+    if (D_ < 64) throw std::invalid_argument("modulus degree too small");
+    nw_ = size_t(D_ + 63) / 64;
+    // barrett_ = floor(t^(2D) / mu) by long division, highest quotient bit first.
+    Words rem((size_t(2 * D_) / 64) + 2, 0);
+    rem[size_t(2 * D_) / 64] |= 1ull << (2 * D_ % 64);
+    Words q(size_t(D_) / 64 + 2, 0);
+    for (int i = 2 * D_; i >= D_; i--) {
+        if (!((rem[size_t(i) / 64] >> (i % 64)) & 1u)) continue;
+        const int s = i - D_;
+        q[size_t(s) / 64] |= 1ull << (s % 64);
+        const size_t wo = size_t(s) / 64;
+        const int bo = s % 64;
+        for (size_t j = 0; j < mu_.size(); j++) {
+            rem[j + wo] ^= mu_[j] << bo;
+            if (bo && j + wo + 1 < rem.size()) rem[j + wo + 1] ^= mu_[j] >> (64 - bo);
+        }
+    }
+    poly_trim(q);
+    barrett_ = q;
+}
+
+Words PolyMod::reduce(const Words& a_in) const {
+    Words a(a_in);
+    poly_trim(a);
+    if (poly_degree(a) < D_) {
+        a.resize(nw_, 0);
+        return a;
+    }
+    // quotient = floor(floor(a / t^D) * floor(t^2D / mu) / t^D), exact for deg a < 2D
+    Words hi = shr_bits(a, D_);
+    Words q = shr_bits(poly_mul(hi, barrett_), D_);
+    poly_trim(q);
+    Words qm = poly_mul(q, mu_);
+    Words r(nw_, 0);
+    for (size_t i = 0; i < nw_; i++) r[i] = (i < a.size() ? a[i] : 0) ^ (i < qm.size() ? qm[i] : 0);
+    if (D_ % 64) r[nw_ - 1] &= (1ull << (D_ % 64)) - 1;
+    return r;
+}
+
+Words PolyMod::sqr(const Words& a) const {
+    // squaring over GF(2) spreads the bits: (sum a_i t^i)^2 = sum a_i t^(2i)
+    Words s(2 * a.size(), 0);
+    for (size_t i = 0; i < a.size(); i++) {
+        __m128i v = _mm_cvtsi64_si128((long long)a[i]);
+        __m128i p = _mm_clmulepi64_si128(v, v, 0x00);
+        s[2 * i] = (uint64_t)_mm_cvtsi128_si64(p);
+        s[2 * i + 1] = (uint64_t)_mm_extract_epi64(p, 1);
+    }
+    return reduce(s);
+}
+
+Words PolyMod::mul(const Words& a, const Words& b) const { return reduce(poly_mul(a, b)); }
+
+Words PolyMod::mul_t(const Words& a_in) const {
+    Words a(a_in);
+    a.resize(nw_ + 1, 0);
+    for (size_t i = a.size(); i-- > 1;) a[i] = (a[i] << 1) | (a[i - 1] >> 63);
+    a[0] <<= 1;
+    if ((a[size_t(D_) / 64] >> (D_ % 64)) & 1u)
+        for (size_t j = 0; j < mu_.size(); j++) a[j] ^= mu_[j];
+    a.resize(nw_);
+    return a;
+}
+
+Words PolyMod::t_pow2(uint64_t k, const Words* start) const {
+    Words cur;
+    if (start) {
+        cur = reduce(*start);
+    } else {
+        cur.assign(nw_, 0);
+        cur[0] = 2;
+    }
+    for (uint64_t i = 0; i < k; i++) cur = sqr(cur);
+    return cur;
+}
+
+Words PolyMod::t_pow(const uint64_t* e, size_t e_words) const {
+    Words acc(nw_, 0);
+    acc[0] = 1;
+    int top = -1;
+    for (size_t i = e_words; i-- > 0;)
+        if (e[i]) {
+            top = int(i * 64 + 63 - __builtin_clzll(e[i]));
+            break;
+        }
+    for (int i = top; i >= 0; i--) {
+        acc = sqr(acc);
+        if ((e[size_t(i) / 64] >> (i % 64)) & 1u) acc = mul_t(acc);
+    }
+    return acc;
+}
+
+// ---- Berlekamp-Massey ---------------------------------------------------------
+
+Words berlekamp_massey(const std::vector<uint8_t>& s) {
+    const size_t N = s.size();
+    const size_t W = N / 64 + 2;
+    // rev: bit (N - 1 - i) holds s_i, so bits [N-1-n, N-1-n+L] read s_n, s_{n-1}, ..., s_{n-L}
+    Words rev(W + 1, 0);
+    for (size_t i = 0; i < N; i++)
+        if (s[i]) {
+            const size_t b = N - 1 - i;
+            rev[b / 64] |= 1ull << (b % 64);
+        }
+    Words C(W, 0), B(W, 0), T;
+    C[0] = 1;
+    B[0] = 1;
+    size_t L = 0, m = 1;
+    for (size_t n = 0; n < N; n++) {
+        // d = sum_{i=0..L} c_i s_{n-i}
+        const size_t base = N - 1 - n;
+        const size_t nw = L / 64 + 1;
+        uint64_t acc = 0;
+        for (size_t w = 0; w < nw; w++) {
+            const size_t bit = base + 64 * w;
+            const size_t wi = bit / 64, bo = bit % 64;
+            uint64_t win = rev[wi] >> bo;
+            if (bo && wi + 1 < rev.size()) win |= rev[wi + 1] << (64 - bo);
+            acc ^= C[w] & win;
+        }
+        if (!__builtin_parityll(acc)) {
+            m++;
+            continue;
+        }
+        const bool grow = 2 * L <= n;
+        if (grow) T = C;
+        const size_t wo = m / 64, bo = m % 64;
+        for (size_t w = 0; w + wo < W; w++) {
+            C[w + wo] ^= B[w] << bo;
+            if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
+        }
+        if (grow) {
+            L = n + 1 - L;
+            B.swap(T);
+            m = 1;
+        } else {
+            m++;
+        }
+    }
+    // characteristic orientation: mu_j = c_{L-j}
+    Words mu(L / 64 + 1, 0);
+    for (size_t j = 0; j <= L; j++) {
+        const size_t i = L - j;
+        if ((C[i / 64] >> (i % 64)) & 1u) mu[j / 64] |= 1ull << (j % 64);
+    }
+    return mu;
+}
+
+// ---- raw bit sequences of the base generators (block regeneration form) ------
+
+static std::vector<uint8_t> raw_bits(int variant, size_t count) {
+    std::vector<uint8_t> bits;
+    bits.reserve(count);
+    if (variant == 0) {
+        const int n = 624, m = 397;
+        uint32_t x[624];
+        x[0] = 20230928u;
+        for (int i = 1; i < n; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + uint32_t(i);
+        while (bits.size() < count) {
+            for (int k = 0; k < n; k++) {  // eq. (stepnomod): in place, indices mod n
+                const uint32_t y = (x[k] & 0x80000000u) | (x[(k + 1) % n] & 0x7fffffffu);
+                x[k] = x[(k + m) % n] ^ (y >> 1) ^ ((y & 1u) ? 0x9908B0DFu : 0u);
+            }
+            for (int k = 0; k < n && bits.size() < count; k++) bits.push_back(uint8_t(x[k] & 1u));
+        }
+    } else if (variant == 1) {
+        const int n = 312, m = 156;
+        uint64_t x[312];
+        x[0] = 20230928u;
+        for (int i = 1; i < n; i++)
+            x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + uint64_t(i);
+        while (bits.size() < count) {
+            for (int k = 0; k < n; k++) {
+                const uint64_t y = (x[k] & 0xFFFFFFFF80000000ull) | (x[(k + 1) % n] & 0x7FFFFFFFull);
+                x[k] = x[(k + m) % n] ^ (y >> 1) ^ ((y & 1u) ? 0xB5026F5AA96619E9ull : 0ull);
+            }
+            for (int k = 0; k < n && bits.size() < count; k++) bits.push_back(uint8_t(x[k] & 1u));
+        }
+    } else {
+        const int N = 156, m = 122;
+        static const uint32_t K[4] = {0xDFFFFFEFu, 0xDDFECB7Fu, 0xBFFAFFFFu, 0xBFFFFFF6u};
+        unsigned __int128 w[156];
+        uint32_t s32[624];
+        s32[0] = 20230928u;
+        for (int i = 1; i < 624; i++) s32[i] = 1812433253u * (s32[i - 1] ^ (s32[i - 1] >> 30)) + uint32_t(i);
+        for (int k = 0; k < N; k++)
+            w[k] = (unsigned __int128)s32[4 * k] | ((unsigned __int128)s32[4 * k + 1] << 32) |
+                   ((unsigned __int128)s32[4 * k + 2] << 64) | ((unsigned __int128)s32[4 * k + 3] << 96);
+        auto sub = [](unsigned __int128 v, int j) { return uint32_t(v >> (32 * j)); };
+        while (bits.size() < count) {
+            for (int k = 0; k < N; k++) {
+                const unsigned __int128 a = w[k], b = w[(k + m) % N], c = w[(k + N - 2) % N], d = w[(k + N - 1) % N];
+                unsigned __int128 bm = 0, dl = 0;
+                for (int j = 0; j < 4; j++) {
+                    bm |= (unsigned __int128)((sub(b, j) >> 11) & K[j]) << (32 * j);
+                    dl |= (unsigned __int128)(sub(d, j) << 18) << (32 * j);
+                }
+                w[k] = a ^ (a << 8) ^ bm ^ (c >> 8) ^ dl;
+            }
+            for (int k = 0; k < N && bits.size() < count; k++) bits.push_back(uint8_t(uint32_t(w[k]) & 1u));
+        }
+    }
+    return bits;
+}
+
+Words generator_minpoly(int variant) {
+    const size_t terms = 2 * 19968 + 256;
+    Words mu = berlekamp_massey(raw_bits(variant, terms));
+    poly_trim(mu);
+    return mu;
+}
+
+}  // namespace vmt

@@ -1,0 +1,679 @@
+// vmt_capi.cpp -- the C ABI declared in include/vmt.h.
+//
+// Host side of the runtime: argument checks, the state registry, the jump
+// polynomials (computed here on the CPU with gf2poly, applied on the GPU),
+// task lists for batched calls, and kernel launches on the caller's stream.
+#include "vmt.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "gf2poly.hpp"
+#include "vmt_common.hpp"
+#include "vmt_launch.hpp"
+
+using vmt::Words;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(VMT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_M(uint32_t M) { return M >= 1 && M <= 64 && (M & (M - 1)) == 0; }
+bool valid_variant(int v) { return v == VMT_MT32 || v == VMT_MT64 || v == VMT_SFMT; }
+int log2u(uint32_t M) { return 31 - __builtin_clz(M); }
+
+struct StateInfo {
+    int variant;
+    uint32_t M;
+};
+
+struct DevPoly {
+    uint64_t* d = nullptr;  // kPolyWords words on the device
+    uint32_t deg = 0;
+};
+
+struct LaneTable {
+    uint64_t* d = nullptr;  // M slots of kPolyWords words
+    uint32_t max_deg = 0;
+};
+
+}  // namespace
+
+struct vmt_ctx {
+    int device = -1;
+    std::mutex mu;
+    std::unordered_map<const void*, StateInfo> reg;
+    std::unique_ptr<vmt::PolyMod> ring[3];
+    std::map<uint64_t, Words> pow2[3];                 // k -> t^(2^k) mod mu
+    std::map<uint32_t, LaneTable> lanes[3];            // M -> lane polynomials on the device
+    std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device
+    uint32_t lpw[3] = {0, 0, 0};
+};
+
+struct vmt_batch_plan {
+    vmt_ctx* ctx;
+    int variant;
+    uint32_t M;
+    int out_kind;
+    uint32_t count;
+    uint32_t grid;
+    vmt::BatchTask* d_tasks;
+    uint32_t* d_counter;
+};
+
+namespace {
+
+int set_device(vmt_ctx* ctx) {
+    if (!ctx) return fail(VMT_EINVAL, "null context");
+    if (ctx->device < 0) return fail(VMT_EDEVICE, "host-only context (created with device -1)");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return VMT_OK;
+}
+
+// ---- polynomials (caller holds ctx->mu) ---------------------------------------
+
+vmt::PolyMod& ring(vmt_ctx* ctx, int variant) {
+    if (!ctx->ring[variant]) ctx->ring[variant].reset(new vmt::PolyMod(vmt::generator_minpoly(variant)));
+    return *ctx->ring[variant];
+}
+
+// t^(2^k) mod mu, extending the cached squaring chain from the nearest k below.
+const Words& pow2(vmt_ctx* ctx, int variant, uint64_t k) {
+    auto& cache = ctx->pow2[variant];
+    auto it = cache.find(k);
+    if (it != cache.end()) return it->second;
+    vmt::PolyMod& R = ring(ctx, variant);
+    auto below = cache.lower_bound(k);
+    Words cur;
+    uint64_t from = 0;
+    if (below != cache.begin()) {
+        --below;
+        cur = below->second;
+        from = below->first;
+    } else {
+        cur.assign(R.words(), 0);
+        cur[0] = 2;  // t
+    }
+    for (uint64_t i = from; i < k; i++) {
+        cur = R.sqr(cur);
+        if (i + 1 <= 512 || (i + 1) % 1024 == 0) cache[i + 1] = cur;  // keep small k and checkpoints
+    }
+    cache[k] = cur;
+    return cache[k];
+}
+
+int upload_poly(const Words& p, DevPoly* out) {
+    std::vector<uint64_t> buf(vmt::kPolyWords, 0);
+    const int deg = vmt::poly_degree(p);
+    if (deg >= vmt::kPolyWords * 64) return fail(VMT_EINVAL, "polynomial too large");
+    std::copy(p.begin(), p.begin() + std::min(p.size(), buf.size()), buf.begin());
+    hipError_t e = hipMalloc(&out->d, buf.size() * 8);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(poly): %s", hipGetErrorString(e));
+    e = hipMemcpy(out->d, buf.data(), buf.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(poly)");
+    out->deg = deg < 0 ? 0 : uint32_t(deg);
+    return VMT_OK;
+}
+
+// Lane polynomials t^(t J) mod mu, t = 0..M-1, J = 2^(19937 - log2 M) (Sec. 3, Table jvalues).
+int lane_table(vmt_ctx* ctx, int variant, uint32_t M, LaneTable** out) {
+    auto it = ctx->lanes[variant].find(M);
+    if (it != ctx->lanes[variant].end()) {
+        *out = &it->second;
+        return VMT_OK;
+    }
+    vmt::PolyMod& R = ring(ctx, variant);
+    std::vector<uint64_t> host((size_t)M * vmt::kPolyWords, 0);
+    host[0] = 1;  // lane 0: t^0
+    uint32_t max_deg = 0;
+    if (M > 1) {
+        const Words gJ = pow2(ctx, variant, 19937u - (uint32_t)log2u(M));
+        Words g = gJ;
+        for (uint32_t t = 1; t < M; t++) {
+            if (t > 1) g = R.mul(g, gJ);
+            const int d = vmt::poly_degree(g);
+            max_deg = std::max<uint32_t>(max_deg, d < 0 ? 0 : uint32_t(d));
+            std::copy(g.begin(), g.begin() + std::min<size_t>(g.size(), vmt::kPolyWords),
+                      host.begin() + (size_t)t * vmt::kPolyWords);
+        }
+    }
+    LaneTable lt;
+    lt.max_deg = max_deg;
+    hipError_t e = hipMalloc(&lt.d, host.size() * 8);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(lane table): %s", hipGetErrorString(e));
+    e = hipMemcpy(lt.d, host.data(), host.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(lane table)");
+    auto res = ctx->lanes[variant].emplace(M, lt);
+    *out = &res.first->second;
+    return VMT_OK;
+}
+
+// Device copy of t^d mod mu, cached per distance.
+int jump_table(vmt_ctx* ctx, int variant, const std::vector<uint64_t>& dist, const Words* known, DevPoly** out) {
+    auto& cache = ctx->jumps[variant];
+    auto it = cache.find(dist);
+    if (it != cache.end()) {
+        *out = &it->second;
+        return VMT_OK;
+    }
+    if (cache.size() >= 4096) {  // bound the cache; entries may be in use by queued kernels
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        for (auto& kv : cache) (void)hipFree(kv.second.d);
+        cache.clear();
+    }
+    Words g = known ? *known : ring(ctx, variant).t_pow(dist.data(), dist.size());
+    DevPoly dp;
+    int st = upload_poly(g, &dp);
+    if (st) return st;
+    auto res = cache.emplace(dist, dp);
+    *out = &res.first->second;
+    return VMT_OK;
+}
+
+int lookup(vmt_ctx* ctx, const void* d_state, StateInfo* info) {
+    if (!d_state) return fail(VMT_EINVAL, "null state");
+    auto it = ctx->reg.find(d_state);
+    if (it == ctx->reg.end())
+        return fail(VMT_ESTATE, "state %p was not initialised or imported through this context", d_state);
+    *info = it->second;
+    return VMT_OK;
+}
+
+uint32_t pick_lpw(vmt_ctx* ctx, int variant, uint32_t M) {
+    uint32_t l = ctx->lpw[variant];
+    if (l && l <= M && M % l == 0 && l <= 16) return l;
+    return M < 16 ? M : 16;
+}
+
+int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lookup(ctx, d_state, &info);
+        if (st) return st;
+    }
+    if (n == 0) return VMT_OK;
+    if (!d_out) return fail(VMT_EINVAL, "null output");
+    const uint32_t lpw = pick_lpw(ctx, info.variant, info.M);
+    if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
+        return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
+    hipError_t e = vmt::launch_generate(info.variant, info.M, lpw, out_kind, static_cast<uint8_t*>(d_state), d_out,
+                                        n, stream);
+    if (e != hipSuccess) return hip_fail(e, "generate launch");
+    return VMT_OK;
+}
+
+int init_common(vmt_ctx* ctx, int variant, uint32_t M, void* d_state, const vmt::InitTask& task, hipStream_t stream) {
+    LaneTable* lt = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        int st = lane_table(ctx, variant, M, &lt);
+        if (st) return st;
+    }
+    hipError_t e = vmt::launch_init(variant, M, nullptr, task, 1, lt->d, lt->max_deg, stream);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->reg[d_state] = StateInfo{variant, M};
+    return VMT_OK;
+}
+
+int jump_with(vmt_ctx* ctx, void* d_state, const std::vector<uint64_t>& dist, const Words* known, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info;
+    DevPoly* dp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lookup(ctx, d_state, &info);
+        if (st) return st;
+        st = jump_table(ctx, info.variant, dist, known, &dp);
+        if (st) return st;
+    }
+    vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg};
+    hipError_t e = vmt::launch_jump(info.variant, info.M, nullptr, task, 1, stream);
+    if (e != hipSuccess) return hip_fail(e, "jump launch");
+    return VMT_OK;
+}
+
+int check_batch(vmt_ctx* ctx, void* const* d_states, size_t count, StateInfo* common) {
+    if (!d_states) return fail(VMT_EINVAL, "null state array");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (size_t i = 0; i < count; i++) {
+        StateInfo info;
+        int st = lookup(ctx, d_states[i], &info);
+        if (st) return st;
+        if (i == 0) *common = info;
+        else if (info.variant != common->variant || info.M != common->M)
+            return fail(VMT_EINVAL, "batch mixes variants or lane counts (state %zu)", i);
+    }
+    return VMT_OK;
+}
+
+// Task list sorted longest first (LPT order for the persistent kernel).
+std::vector<vmt::BatchTask> batch_tasks(void* const* d_states, const uint64_t* lens, void* const* d_outs, size_t count) {
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lens[a] > lens[b]; });
+    std::vector<vmt::BatchTask> tasks;
+    tasks.reserve(count);
+    for (uint32_t i : order) tasks.push_back(vmt::BatchTask{static_cast<uint8_t*>(d_states[i]), d_outs[i], lens[i]});
+    return tasks;
+}
+
+int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs, size_t count,
+                        int out_kind, StateInfo* info) {
+    if (count == 0) return VMT_OK;
+    if (!lens || !d_outs) return fail(VMT_EINVAL, "null lens or output array");
+    if (count > 0xFFFFFFFFull) return fail(VMT_EINVAL, "too many tasks");
+    int st = check_batch(ctx, d_states, count, info);
+    if (st) return st;
+    if (!vmt::batch_supported(info->variant, info->M, out_kind))
+        return fail(VMT_EVARIANT, "batched output kind %d not available for variant %d with M=%u", out_kind,
+                    info->variant, info->M);
+    {
+        std::vector<const void*> seen(d_states, d_states + count);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(VMT_EINVAL, "a state appears twice in one batch");
+    }
+    for (size_t i = 0; i < count; i++)
+        if (lens[i] && !d_outs[i]) return fail(VMT_EINVAL, "null output for task %zu", i);
+    return VMT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vmt_last_error(void) { return g_err.c_str(); }
+
+const char* vmt_version(void) { return "vmt-mi355x 0.1 (gfx950)"; }
+
+vmt_ctx* vmt_ctx_create(int device, int* status) {
+    std::unique_ptr<vmt_ctx> ctx(new (std::nothrow) vmt_ctx);
+    if (!ctx) {
+        if (status) *status = fail(VMT_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    ctx->device = device;
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || device >= n) {
+            if (status) *status = fail(VMT_EDEVICE, "no HIP device %d (%s)", device, hipGetErrorString(e));
+            return nullptr;
+        }
+        e = hipSetDevice(device);
+        if (e != hipSuccess) {
+            if (status) *status = hip_fail(e, "hipSetDevice");
+            return nullptr;
+        }
+    }
+    if (status) *status = VMT_OK;
+    return ctx.release();
+}
+
+int vmt_ctx_destroy(vmt_ctx* ctx) {
+    if (!ctx) return fail(VMT_EINVAL, "null context");
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (int v = 0; v < 3; v++) {
+            for (auto& kv : ctx->lanes[v]) (void)hipFree(kv.second.d);
+            for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
+        }
+    }
+    delete ctx;
+    return VMT_OK;
+}
+
+size_t vmt_state_bytes(int variant, uint32_t M) {
+    if (!valid_variant(variant) || !valid_M(M)) return 0;
+    return vmt::kHeaderBytes + (size_t)vmt::words_per_lane(variant) * M * vmt::word_bytes(variant);
+}
+
+int vmt_init_genrand(vmt_ctx* ctx, int variant, uint64_t seed, uint32_t M, void* d_state, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    if (!d_state || (uintptr_t)d_state % 256) return fail(VMT_EINVAL, "state must be non-null and 256-byte aligned");
+    vmt::InitTask task{static_cast<uint8_t*>(d_state), nullptr, seed, vmt::kSeedGenrand, 0};
+    return init_common(ctx, variant, M, d_state, task, stream);
+}
+
+int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key_len, uint32_t M, void* d_state,
+                      hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (variant != VMT_MT32) return fail(VMT_EVARIANT, "init_by_array is defined for MT19937-32 only");
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    if (!key || key_len == 0 || key_len > 4096) return fail(VMT_EINVAL, "key must have 1..4096 words");
+    if (!d_state || (uintptr_t)d_state % 256) return fail(VMT_EINVAL, "state must be non-null and 256-byte aligned");
+    void* d_key = nullptr;
+    hipError_t e = hipMallocAsync(&d_key, key_len * 4, stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(key): %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d_key, key, key_len * 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(d_key, stream);
+        return hip_fail(e, "hipMemcpyAsync(key)");
+    }
+    vmt::InitTask task{static_cast<uint8_t*>(d_state), static_cast<const uint32_t*>(d_key), 0, vmt::kSeedByArray,
+                       (uint32_t)key_len};
+    st = init_common(ctx, variant, M, d_state, task, stream);
+    (void)hipFreeAsync(d_key, stream);
+    return st;
+}
+
+int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, size_t count, uint32_t M,
+                            void* const* d_states, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    if (count == 0) return VMT_OK;
+    if (!keys || !d_states || key_len == 0 || key_len > 4096) return fail(VMT_EINVAL, "bad keys");
+    if (count > (1u << 24)) return fail(VMT_EINVAL, "too many states");
+    for (size_t i = 0; i < count; i++)
+        if (!d_states[i] || (uintptr_t)d_states[i] % 256) return fail(VMT_EINVAL, "state %zu null or misaligned", i);
+    LaneTable* lt = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lane_table(ctx, VMT_MT32, M, &lt);
+        if (st) return st;
+    }
+    const size_t key_bytes = count * key_len * 4, task_bytes = count * sizeof(vmt::InitTask);
+    uint8_t* d_buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_buf, key_bytes + task_bytes + 16, stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(init batch): %s", hipGetErrorString(e));
+    const uint32_t* d_keys = reinterpret_cast<const uint32_t*>(d_buf);
+    vmt::InitTask* d_tasks = reinterpret_cast<vmt::InitTask*>(d_buf + ((key_bytes + 15) / 16) * 16);
+    std::vector<vmt::InitTask> tasks(count);
+    for (size_t i = 0; i < count; i++)
+        tasks[i] = vmt::InitTask{static_cast<uint8_t*>(d_states[i]), d_keys + i * key_len, 0, vmt::kSeedByArray,
+                                 (uint32_t)key_len};
+    e = hipMemcpyAsync(d_buf, keys, key_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tasks, tasks.data(), task_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = vmt::launch_init(VMT_MT32, M, d_tasks, tasks[0], (uint32_t)count, lt->d, lt->max_deg, stream);
+    (void)hipFreeAsync(d_buf, stream);
+    if (e != hipSuccess) return hip_fail(e, "init batch");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (size_t i = 0; i < count; i++) ctx->reg[d_states[i]] = StateInfo{VMT_MT32, M};
+    return VMT_OK;
+}
+
+int vmt_jump(vmt_ctx* ctx, void* d_state, const uint64_t* dist_le, size_t dist_words, hipStream_t stream) {
+    if (!dist_le || dist_words == 0 || dist_words > 320) return fail(VMT_EINVAL, "distance needs 1..320 words");
+    std::vector<uint64_t> d(dist_le, dist_le + dist_words);
+    while (d.size() > 1 && d.back() == 0) d.pop_back();
+    if (d.size() == 1 && d[0] == 0) {
+        int st = set_device(ctx);
+        if (st) return st;
+        StateInfo info;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        return lookup(ctx, d_state, &info);  // jump by 0: nothing to do
+    }
+    return jump_with(ctx, d_state, d, nullptr, stream);
+}
+
+int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream) {
+    if (k > 65536) return fail(VMT_EINVAL, "k must be <= 65536");
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info;
+    Words g;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lookup(ctx, d_state, &info);
+        if (st) return st;
+        g = pow2(ctx, info.variant, k);
+    }
+    std::vector<uint64_t> key = {~0ull, k};  // distinct from any plain distance key
+    return jump_with(ctx, d_state, key, &g, stream);
+}
+
+int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (count == 0) return VMT_OK;
+    if (!ks) return fail(VMT_EINVAL, "null ks");
+    StateInfo info;
+    st = check_batch(ctx, d_states, count, &info);
+    if (st) return st;
+    std::vector<vmt::JumpTask> tasks(count);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (size_t i = 0; i < count; i++) {
+            if (ks[i] > 65536) return fail(VMT_EINVAL, "k must be <= 65536");
+            const Words& g = pow2(ctx, info.variant, ks[i]);
+            DevPoly* dp = nullptr;
+            std::vector<uint64_t> key = {~0ull, ks[i]};
+            st = jump_table(ctx, info.variant, key, &g, &dp);
+            if (st) return st;
+            tasks[i] = vmt::JumpTask{static_cast<uint8_t*>(d_states[i]), dp->d, 0u, dp->deg};
+        }
+    }
+    vmt::JumpTask* d_tasks = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_tasks, count * sizeof(vmt::JumpTask), stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(jump tasks): %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d_tasks, tasks.data(), count * sizeof(vmt::JumpTask), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = vmt::launch_jump(info.variant, info.M, d_tasks, tasks[0], (uint32_t)count, stream);
+    (void)hipFreeAsync(d_tasks, stream);
+    if (e != hipSuccess) return hip_fail(e, "jump batch");
+    return VMT_OK;
+}
+
+int vmt_generate_u32(vmt_ctx* ctx, void* d_state, size_t n, uint32_t* d_out, hipStream_t stream) {
+    return generate(ctx, d_state, n, d_out, vmt::kOutU32, stream);
+}
+int vmt_generate_u64(vmt_ctx* ctx, void* d_state, size_t n, uint64_t* d_out, hipStream_t stream) {
+    return generate(ctx, d_state, n, d_out, vmt::kOutU64, stream);
+}
+int vmt_uniform_f32(vmt_ctx* ctx, void* d_state, size_t n, float* d_out, hipStream_t stream) {
+    return generate(ctx, d_state, n, d_out, vmt::kOutF32, stream);
+}
+int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStream_t stream) {
+    return generate(ctx, d_state, n, d_out, vmt::kOutF64, stream);
+}
+
+int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs, size_t count,
+                       int out_kind, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info{};
+    st = validate_batch_args(ctx, d_states, lens, d_outs, count, out_kind, &info);
+    if (st || count == 0) return st;
+    std::vector<vmt::BatchTask> tasks = batch_tasks(d_states, lens, d_outs, count);
+    const size_t bytes = count * sizeof(vmt::BatchTask);
+    uint8_t* d_buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_buf, bytes + 256, stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(batch): %s", hipGetErrorString(e));
+    vmt::BatchTask* d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
+    uint32_t* d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
+    e = hipMemcpyAsync(d_tasks, tasks.data(), bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        const uint32_t grid = vmt::batch_grid(info.variant, info.M, out_kind, ctx->device);
+        e = vmt::launch_batch(info.variant, info.M, out_kind, d_tasks, (uint32_t)count, d_counter, grid, stream);
+    }
+    (void)hipFreeAsync(d_buf, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return VMT_OK;
+}
+
+vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
+                                      size_t count, int out_kind, int* status) {
+    int st = set_device(ctx);
+    StateInfo info{};
+    if (!st && count == 0) st = fail(VMT_EINVAL, "empty plan");
+    if (!st) st = validate_batch_args(ctx, d_states, lens, d_outs, count, out_kind, &info);
+    if (st) {
+        if (status) *status = st;
+        return nullptr;
+    }
+    std::vector<vmt::BatchTask> tasks = batch_tasks(d_states, lens, d_outs, count);
+    const size_t bytes = count * sizeof(vmt::BatchTask);
+    uint8_t* d_buf = nullptr;
+    hipError_t e = hipMalloc((void**)&d_buf, bytes + 256);
+    if (e != hipSuccess) {
+        if (status) *status = fail(VMT_ENOMEM, "hipMalloc(plan): %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    e = hipMemcpy(d_buf, tasks.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_buf);
+        if (status) *status = hip_fail(e, "hipMemcpy(plan)");
+        return nullptr;
+    }
+    vmt_batch_plan* plan = new vmt_batch_plan;
+    plan->ctx = ctx;
+    plan->variant = info.variant;
+    plan->M = info.M;
+    plan->out_kind = out_kind;
+    plan->count = (uint32_t)count;
+    plan->grid = vmt::batch_grid(info.variant, info.M, out_kind, ctx->device);
+    plan->d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
+    plan->d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
+    if (status) *status = VMT_OK;
+    return plan;
+}
+
+int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream) {
+    if (!plan) return fail(VMT_EINVAL, "null plan");
+    int st = set_device(plan->ctx);
+    if (st) return st;
+    hipError_t e = vmt::launch_batch(plan->variant, plan->M, plan->out_kind, plan->d_tasks, plan->count,
+                                     plan->d_counter, plan->grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return VMT_OK;
+}
+
+int vmt_batch_plan_destroy(vmt_batch_plan* plan) {
+    if (!plan) return fail(VMT_EINVAL, "null plan");
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->d_tasks);
+    delete plan;
+    return VMT_OK;
+}
+
+int vmt_state_export(vmt_ctx* ctx, const void* d_state, void* h_buf, size_t bytes, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lookup(ctx, d_state, &info);
+        if (st) return st;
+    }
+    if (!h_buf || bytes != vmt_state_bytes(info.variant, info.M))
+        return fail(VMT_EINVAL, "buffer must hold exactly vmt_state_bytes = %zu bytes",
+                    vmt_state_bytes(info.variant, info.M));
+    hipError_t e = hipMemcpyAsync(h_buf, d_state, bytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "export");
+    return VMT_OK;
+}
+
+int vmt_state_import(vmt_ctx* ctx, void* d_state, const void* h_buf, size_t bytes, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (!d_state || !h_buf || (uintptr_t)d_state % 256) return fail(VMT_EINVAL, "null or misaligned buffer");
+    if (bytes < vmt::kHeaderBytes) return fail(VMT_EINVAL, "buffer smaller than a header");
+    vmt::StateHeader h;
+    std::memcpy(&h, h_buf, sizeof h);
+    if (h.magic != vmt::kMagic || h.version != vmt::kVersion) return fail(VMT_ESTATE, "not a vmt state (magic/version)");
+    if (!valid_variant((int)h.variant) || !valid_M(h.M)) return fail(VMT_ESTATE, "bad variant or M in header");
+    if (h.n != vmt::words_per_lane(h.variant) || h.word_bytes != vmt::word_bytes(h.variant) ||
+        h.block != h.n * h.M * vmt::elems_per_word(h.variant) || h.pos > h.block)
+        return fail(VMT_ESTATE, "inconsistent header");
+    if (bytes != vmt_state_bytes((int)h.variant, h.M)) return fail(VMT_EINVAL, "size does not match header");
+    hipError_t e = hipMemcpyAsync(d_state, h_buf, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "import");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->reg[d_state] = StateInfo{(int)h.variant, h.M};
+    return VMT_OK;
+}
+
+int vmt_state_release(vmt_ctx* ctx, const void* d_state) {
+    if (!ctx || !d_state) return fail(VMT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->reg.erase(d_state) == 0) return fail(VMT_ESTATE, "state %p is not registered", d_state);
+    return VMT_OK;
+}
+
+int vmt_minpoly(vmt_ctx* ctx, int variant, uint64_t* out, size_t cap, int* degree) {
+    if (!ctx || !out) return fail(VMT_EINVAL, "null argument");
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const Words& mu = ring(ctx, variant).modulus();
+    if (cap < mu.size()) return fail(VMT_EINVAL, "need %zu words", mu.size());
+    std::fill(out, out + cap, 0);
+    std::copy(mu.begin(), mu.end(), out);
+    if (degree) *degree = vmt::poly_degree(mu);
+    return VMT_OK;
+}
+
+int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dist_words, uint64_t* out, size_t cap,
+                  int* degree) {
+    if (!ctx || !out || !dist_le || dist_words == 0) return fail(VMT_EINVAL, "null argument");
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    vmt::PolyMod& R = ring(ctx, variant);
+    Words g;
+    // a single set bit: use the cached squaring chain
+    int bits = 0, top = -1;
+    for (size_t i = 0; i < dist_words; i++) {
+        bits += __builtin_popcountll(dist_le[i]);
+        if (dist_le[i]) top = int(i * 64 + 63 - __builtin_clzll(dist_le[i]));
+    }
+    if (bits == 1) g = pow2(ctx, variant, (uint64_t)top);
+    else g = R.t_pow(dist_le, dist_words);
+    if (cap < g.size()) return fail(VMT_EINVAL, "need %zu words", g.size());
+    std::fill(out, out + cap, 0);
+    std::copy(g.begin(), g.end(), out);
+    if (degree) *degree = vmt::poly_degree(g);
+    return VMT_OK;
+}
+
+int vmt_set_tuning(vmt_ctx* ctx, int variant, uint32_t lanes_per_wg, uint32_t threads) {
+    if (!ctx) return fail(VMT_EINVAL, "null context");
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    if (lanes_per_wg && (!valid_M(lanes_per_wg) || lanes_per_wg > 16))
+        return fail(VMT_EINVAL, "lanes per workgroup must be 0 or a power of two <= 16");
+    (void)threads;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->lpw[variant] = lanes_per_wg;
+    return VMT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,897 @@
+// vmt_kernels.hip -- gfx950 kernels for the V-family generators.
+//
+// Paper: F. Cannizzo, "VMT19937: A SIMD-Friendly Pseudo Random Number
+// Generator based on Mersenne Twister 19937" (arXiv 2309.16682).
+//
+// The paper vectorises the twist across M lock-stepped instances in one SIMD
+// register (Sec. 3, eq. msmt19937). On CDNA4 the same idea maps onto the
+// 64-wide wavefront: the lane-interleaved window sits in LDS, so row k of the
+// window (word k of every lane) is contiguous, and a work item updates a
+// 16-byte group of lanes of one row with one ds_read_b128 per operand.
+//
+// Block regeneration (Sec. 2.5, eq. stepnomod): the n new words of a block
+// fall into three index ranges, [0, n-m), [n-m, 2(n-m)), [2(n-m), n). Word
+// c of range 1 needs only old words; word c + (n-m) of range 2 needs the new
+// word c; word c + 2(n-m) of range 3 needs the new word c + (n-m). So one
+// work item owns the "column" c, c + (n-m), c + 2(n-m) and carries the
+// dependency in registers: every LDS read is of the old block, every write
+// happens after one barrier. The only cross-column value, new word 0 read by
+// the last word of the block, is recomputed where it is needed.
+//
+// Tempering (eq. tempering) and the optional float map are fused between
+// the twist and the 16-byte global store, so each output is written once,
+// in stream order, by a fully coalesced store.
+//
+// Jump (Sec. 3.1): the state after d steps is g(F) X with g = t^d mod mu.
+// Word j of the new window is the XOR of the raw words x_{i+j} over the set
+// coefficients i of g (Horner's rule unrolled over the word sequence). A
+// workgroup regenerates the raw sequence two blocks at a time in LDS and each
+// wavefront accumulates one lane; the loop over the coefficients of g is
+// wave-uniform (scalar unit), the XORs are VALU.
+#include <hip/hip_runtime.h>
+
+#include "vmt_common.hpp"
+#include "vmt_launch.hpp"
+
+namespace vmt {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Parameters: Sec. 2.2 eq. (params), Sec. 2.3 eq. (params64),
+// Sec. 2.4 eq. (sfmt_params).
+// ---------------------------------------------------------------------------
+
+struct MT32P {
+    using W = uint32_t;
+    static constexpr int N = 624, MM = 397, D = N - MM;  // D = 227
+    static constexpr int V = 4;                            // lanes per 16-byte group
+};
+struct MT64P {
+    using W = uint64_t;
+    static constexpr int N = 312, MM = 156, D = N - MM;  // D = 156
+    static constexpr int V = 2;
+};
+constexpr int kSfmtN = 156, kSfmtM = 122;
+
+// a ^ (b & c) in one VALU op (v_bitop3_b32, truth table 0x78)
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, (unsigned char)0x78);
+}
+// all ones if bit 0 of x is set
+__device__ __forceinline__ uint32_t lsb_mask(uint32_t x) { return (uint32_t)__builtin_amdgcn_sbfe((int)x, 0, 1); }
+
+// Values that are equal in every lane but reach the kernel through memory a
+// lane reads (LDS, a task list) must be marked uniform: loops and exits that
+// contain barriers have to be scalar branches, never exec-masked ones.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform(uint64_t x) {
+    return ((uint64_t)uniform((uint32_t)(x >> 32)) << 32) | uniform((uint32_t)x);
+}
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+    return reinterpret_cast<T*>(uniform((uint64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+// ---- MT19937-32: eq. (step) with eq. (matmult); h = 0x80000000, l = 0x7fffffff.
+// omega = (x_k & h) | (x_{k+1} & l); bit 0 of omega is bit 0 of x_{k+1}.
+__device__ __forceinline__ uint32_t twist(uint32_t xk, uint32_t xk1, uint32_t xkm) {
+    const uint32_t omega = (xk & 0x80000000u) | (xk1 & 0x7fffffffu);
+    return xor_and(xkm ^ (omega >> 1), lsb_mask(xk1), 0x9908B0DFu);
+}
+// eq. (tempering), MT19937-32 constants; d = 0xFFFFFFFF needs no mask.
+__device__ __forceinline__ uint32_t temper(uint32_t y) {
+    y ^= y >> 11;
+    y = xor_and(y, y << 7, 0x9D2C5680u);
+    y = xor_and(y, y << 15, 0xEFC60000u);
+    return y ^ (y >> 18);
+}
+
+// ---- MT19937-64 on 32-bit halves (v_alignbit for the 64-bit shifts):
+// h = 0xFFFFFFFF80000000, l = 0x7FFFFFFF, a = 0xB5026F5AA96619E9.
+__device__ __forceinline__ uint64_t twist(uint64_t xk, uint64_t xk1, uint64_t xkm) {
+    const uint32_t kh = (uint32_t)(xk >> 32), kl = (uint32_t)xk, k1 = (uint32_t)xk1;
+    const uint32_t ol = (kl & 0x80000000u) | (k1 & 0x7fffffffu);  // omega = (kh : ol)
+    const uint32_t odd = lsb_mask(k1);
+    const uint32_t lo = xor_and((uint32_t)xkm ^ __builtin_amdgcn_alignbit(kh, ol, 1), odd, 0xA96619E9u);
+    const uint32_t hi = xor_and((uint32_t)(xkm >> 32) ^ (kh >> 1), odd, 0xB5026F5Au);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t temper(uint64_t y) {
+    uint32_t lo = (uint32_t)y, hi = (uint32_t)(y >> 32);
+    // y ^= (y >> 29) & 0x5555555555555555
+    const uint32_t s1l = __builtin_amdgcn_alignbit(hi, lo, 29), s1h = hi >> 29;
+    lo = xor_and(lo, s1l, 0x55555555u);
+    hi = xor_and(hi, s1h, 0x55555555u);
+    // y ^= (y << 17) & 0x71D67FFFEDA60000
+    const uint32_t s2h = __builtin_amdgcn_alignbit(hi, lo, 15), s2l = lo << 17;
+    lo = xor_and(lo, s2l, 0xEDA60000u);
+    hi = xor_and(hi, s2h, 0x71D67FFFu);
+    // y ^= (y << 37) & 0xFFF7EEE000000000
+    hi = xor_and(hi, lo << 5, 0xFFF7EEE0u);
+    // y ^= y >> 43
+    lo ^= hi >> 11;
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---- SFMT19937, eq. (sfmt_step); 128-bit words as uint4, .x least significant.
+// w <<< 8 moves bits from sub-word j into j + 1; w >>> 8 from j + 1 into j.
+__device__ __forceinline__ uint4 sfmt_next(const uint4 a, const uint4 b, const uint4 c, const uint4 d) {
+    uint4 r;
+    r.x = a.x ^ (a.x << 8) ^ __builtin_amdgcn_alignbit(c.y, c.x, 8);
+    r.y = a.y ^ __builtin_amdgcn_alignbit(a.y, a.x, 24) ^ __builtin_amdgcn_alignbit(c.z, c.y, 8);
+    r.z = a.z ^ __builtin_amdgcn_alignbit(a.z, a.y, 24) ^ __builtin_amdgcn_alignbit(c.w, c.z, 8);
+    r.w = a.w ^ __builtin_amdgcn_alignbit(a.w, a.z, 24) ^ (c.w >> 8);
+    r.x = xor_and(r.x, b.x >> 11, 0xDFFFFFEFu) ^ (d.x << 18);
+    r.y = xor_and(r.y, b.y >> 11, 0xDDFECB7Fu) ^ (d.y << 18);
+    r.z = xor_and(r.z, b.z >> 11, 0xBFFAFFFFu) ^ (d.z << 18);
+    r.w = xor_and(r.w, b.w >> 11, 0xBFFFFFF6u) ^ (d.w << 18);
+    return r;
+}
+
+// ---- fixed float maps (exact: the kept bits fit the significand)
+__device__ __forceinline__ float to_f32(uint32_t u) { return (float)(u >> 8) * 0x1p-24f; }
+__device__ __forceinline__ float to_f32(uint64_t u) { return (float)(uint32_t)(u >> 40) * 0x1p-24f; }
+__device__ __forceinline__ double to_f64(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+
+// output element for a tempered word; OUT: 0 native, 1 f32, 2 f64
+template <int OUT, class W>
+struct OutOf;
+template <class W>
+struct OutOf<0, W> {
+    using T = W;
+    static __device__ __forceinline__ T map(W v) { return v; }
+};
+template <class W>
+struct OutOf<1, W> {
+    using T = float;
+    static __device__ __forceinline__ T map(W v) { return to_f32(v); }
+};
+template <class W>
+struct OutOf<2, W> {
+    using T = double;
+    static __device__ __forceinline__ T map(W v) { return to_f64(v); }
+};
+
+template <class T, int V>
+struct alignas(sizeof(T) * V) Vec {
+    T v[V];
+};
+
+// ---------------------------------------------------------------------------
+// MT generation: one workgroup owns LPW lanes (lanes g*LPW ...) of a state.
+// ---------------------------------------------------------------------------
+
+// Threads per workgroup for LPW lanes: enough whole wavefronts that each
+// thread owns at most two columns (fewer live registers, no spills).
+template <class P, int LPW>
+constexpr int mt_threads() {
+    constexpr int V = LPW < P::V ? LPW : P::V;
+    constexpr int items = P::D * (LPW / V);
+    constexpr int iters = (items + 1023) / 1024;
+    return 64 * ((items + 64 * iters - 1) / (64 * iters));
+}
+
+template <class P, int LPW, int THREADS, int OUT>
+struct MtGen {
+    using W = typename P::W;
+    static constexpr int N = P::N, MM = P::MM, D = P::D;
+    static constexpr int V = LPW < P::V ? LPW : P::V;
+    static constexpr int QPR = LPW / V;  // 16-byte groups per row
+    static constexpr int ITEMS = D * QPR;
+    static constexpr int ITERS = (ITEMS + THREADS - 1) / THREADS;
+    static constexpr bool THREE = N > 2 * D;  // MT19937-32 has a third index range
+    static constexpr size_t LDS_BYTES = sizeof(W) * N * LPW;
+    using VW = Vec<W, V>;
+    using Map = OutOf<OUT, W>;
+    using OutT = typename Map::T;
+    using VO = Vec<OutT, V>;
+
+    static __device__ __forceinline__ VW ld(const W* win, int row, int off) {
+        return *reinterpret_cast<const VW*>(win + row * LPW + off);
+    }
+    static __device__ __forceinline__ void st(W* win, int row, int off, const VW& v) {
+        *reinterpret_cast<VW*>(win + row * LPW + off) = v;
+    }
+    static __device__ __forceinline__ VW twistv(const VW& a, const VW& b, const VW& m) {
+        VW r;
+#pragma unroll
+        for (int j = 0; j < V; j++) r.v[j] = twist(a.v[j], b.v[j], m.v[j]);
+        return r;
+    }
+    // temper, map and store V lanes of one row at element index o (< lim)
+    static __device__ __forceinline__ void out_row(OutT* ob, uint32_t o, uint32_t lim, bool vec_ok, const VW& w) {
+        VO r;
+#pragma unroll
+        for (int j = 0; j < V; j++) r.v[j] = Map::map(temper(w.v[j]));
+        if (vec_ok && o + V <= lim) {
+            *reinterpret_cast<VO*>(ob + o) = r;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; j++)
+                if (o + j < lim) ob[o + j] = r.v[j];
+        }
+    }
+
+    // Emit `len` elements from `state` (lanes g*LPW .. g*LPW + LPW - 1).
+    static __device__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, W* win) {
+        state = uniform(state);
+        out = uniform(out);
+        len = uniform(len);
+        StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
+        const uint32_t M = uniform(hdr->M);
+        const uint32_t pos = uniform(hdr->pos);
+        W* gwin = reinterpret_cast<W*>(state + kHeaderBytes);
+        const uint32_t B = (uint32_t)N * M;
+        if (len == 0) return;
+        const int tid = threadIdx.x;
+        const uint32_t lane0 = g * LPW;
+        const uint64_t head = len < (uint64_t)(B - pos) ? len : (uint64_t)(B - pos);
+        const uint64_t rest = len - head;
+        const uint64_t nblocks = (rest + B - 1) / B;
+
+        for (int i = tid; i < N * QPR; i += THREADS) {
+            const int k = i / QPR, q = i - (i / QPR) * QPR;
+            st(win, k, q * V, *reinterpret_cast<const VW*>(gwin + (size_t)k * M + lane0 + q * V));
+        }
+        __syncthreads();
+
+        if (head) {  // rest of the current block, tempered from the window
+            const uint32_t k0 = pos / M, k1 = (uint32_t)((pos + head - 1) / M);
+            for (uint32_t i = k0 * LPW + tid; i < (k1 + 1) * LPW; i += THREADS) {
+                const uint32_t k = i / LPW, tl = i - (i / LPW) * LPW;
+                const uint32_t e = k * M + lane0 + tl;
+                if (e >= pos && e < pos + head) out[e - pos] = Map::map(temper(win[k * LPW + tl]));
+            }
+        }
+
+        const bool vec_ok = (head % V) == 0 && ((uintptr_t)out % sizeof(VO)) == 0;
+        for (uint64_t b = 0; b < nblocks; ++b) {
+            const uint64_t o0 = head + b * B;
+            OutT* ob = out + o0;
+            const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
+            VW nw[ITERS][THREE ? 3 : 2];
+#pragma unroll
+            for (int s = 0; s < ITERS; ++s) {
+                const int it = tid + s * THREADS;
+                if (it < ITEMS) {
+                    const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
+                    const uint32_t oc = (uint32_t)c * M + lane0 + off;
+                    // range 1: old words only
+                    const VW n0 = twistv(ld(win, c, off), ld(win, c + 1, off), ld(win, c + MM, off));
+                    nw[s][0] = n0;
+                    out_row(ob, oc, lim, vec_ok, n0);
+                    // range 2: x_{k+m-n} is the new word c
+                    const int r1 = c + D;
+                    VW b1;
+                    if (THREE || r1 + 1 < N) {
+                        b1 = ld(win, r1 + 1, off);
+                    } else {  // last word of the block reads the new word 0
+                        b1 = twistv(ld(win, 0, off), ld(win, 1, off), ld(win, MM, off));
+                    }
+                    const VW n1 = twistv(ld(win, r1, off), b1, n0);
+                    nw[s][1] = n1;
+                    out_row(ob, oc + (uint32_t)D * M, lim, vec_ok, n1);
+                    if constexpr (THREE) {
+                        // range 3: x_{k+m-n} is the new word c + D
+                        const int r2 = c + 2 * D;
+                        if (r2 < N) {
+                            VW b2;
+                            if (r2 + 1 < N) b2 = ld(win, r2 + 1, off);
+                            else b2 = twistv(ld(win, 0, off), ld(win, 1, off), ld(win, MM, off));
+                            const VW n2 = twistv(ld(win, r2, off), b2, n1);
+                            nw[s][2] = n2;
+                            out_row(ob, oc + 2u * D * M, lim, vec_ok, n2);
+                        }
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);  // keep the next column's loads from piling up
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < ITERS; ++s) {
+                const int it = tid + s * THREADS;
+                if (it < ITEMS) {
+                    const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
+                    st(win, c, off, nw[s][0]);
+                    st(win, c + D, off, nw[s][1]);
+                    if constexpr (THREE) {
+                        if (c + 2 * D < N) st(win, c + 2 * D, off, nw[s][2]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        if (nblocks) {
+            for (int i = tid; i < N * QPR; i += THREADS) {
+                const int k = i / QPR, q = i - (i / QPR) * QPR;
+                *reinterpret_cast<VW*>(gwin + (size_t)k * M + lane0 + q * V) = ld(win, k, q * V);
+            }
+        }
+        if (write_pos && uniform((uint32_t)tid >> 6) == 0)  // wave 0, same value from every lane
+            hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
+    }
+};
+
+template <class P, int LPW, int OUT>
+__global__ __launch_bounds__((mt_threads<P, LPW>())) void gen_mt_kernel(uint8_t* state, void* out, uint64_t len,
+                                                                     int write_pos) {
+    using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
+    __shared__ __attribute__((aligned(16))) typename P::W win[P::N * LPW];
+    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
+}
+
+// Persistent batched generation: each workgroup pops states from a counter;
+// tasks are sorted longest first by the host.
+template <class P, int LANES, int OUT>
+__global__ __launch_bounds__((mt_threads<P, LANES>())) void batch_mt_kernel(const BatchTask* tasks, uint32_t count,
+                                                                         uint32_t* counter) {
+    using G = MtGen<P, LANES, mt_threads<P, LANES>(), OUT>;
+    __shared__ __attribute__((aligned(16))) typename P::W win[P::N * LANES];
+    __shared__ uint32_t s_task;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    for (;;) {
+        // Wave 0 takes a ticket without lane divergence (lane 0 adds 1, the
+        // others 0): a lane-divergent branch next to the barriers of this loop
+        // lets the compiler rotate the loop so that part of a wave re-enters
+        // the barrier before the ticket is taken.
+        if (wave == 0) {
+            const uint32_t mine = atomicAdd(counter, (threadIdx.x & 63) == 0 ? 1u : 0u);
+            s_task = uniform(mine);
+        }
+        __syncthreads();
+        const uint32_t t = uniform(s_task);  // one task for the whole workgroup
+        __syncthreads();
+        if (t >= count) break;
+        const BatchTask task = tasks[t];
+        G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, 0, true, win);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SFMT generation: one thread per lane runs the lane's serial chain (the
+// recurrence reads the two previous words, Sec. 2.6), lanes in parallel.
+// ---------------------------------------------------------------------------
+
+template <int LPW, int OUT>
+struct SfmtGen {
+    static constexpr int N = kSfmtN, MM = kSfmtM;
+    static constexpr size_t LDS_BYTES = sizeof(uint4) * N * LPW;
+    using OutT = typename OutOf<OUT == 0 ? 0 : 1, uint32_t>::T;
+
+    static __device__ __forceinline__ void out_word(OutT* ob, uint32_t o, uint32_t lim, bool vec_ok, const uint4 w) {
+        OutT r[4];
+        if constexpr (OUT == 0) {
+            r[0] = w.x; r[1] = w.y; r[2] = w.z; r[3] = w.w;
+        } else {
+            r[0] = to_f32(w.x); r[1] = to_f32(w.y); r[2] = to_f32(w.z); r[3] = to_f32(w.w);
+        }
+        if (vec_ok && o + 4 <= lim) {
+            *reinterpret_cast<Vec<OutT, 4>*>(ob + o) = Vec<OutT, 4>{{r[0], r[1], r[2], r[3]}};
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (o + j < lim) ob[o + j] = r[j];
+        }
+    }
+    static __device__ __forceinline__ uint32_t sub(const uint4& w, uint32_t j) {
+        return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
+    }
+
+    static __device__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, uint4* win) {
+        state = uniform(state);
+        out = uniform(out);
+        len = uniform(len);
+        StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
+        const uint32_t M = uniform(hdr->M);
+        const uint32_t pos = uniform(hdr->pos);
+        uint4* gwin = reinterpret_cast<uint4*>(state + kHeaderBytes);
+        const uint32_t B = 4u * N * M;  // uint32 elements per block
+        if (len == 0) return;
+        const int tid = threadIdx.x;
+        const int nthr = blockDim.x;
+        const uint32_t lane0 = g * LPW;
+        const uint64_t head = len < (uint64_t)(B - pos) ? len : (uint64_t)(B - pos);
+        const uint64_t rest = len - head;
+        const uint64_t nblocks = (rest + B - 1) / B;
+
+        for (int i = tid; i < N * LPW; i += nthr) {
+            const int k = i / LPW, t = i - (i / LPW) * LPW;
+            win[k * LPW + t] = gwin[(size_t)k * M + lane0 + t];
+        }
+        __syncthreads();
+        if (head) {
+            const uint32_t e0 = pos / 4, e1 = (uint32_t)((pos + head - 1) / 4);  // 128-bit elements touched
+            const uint32_t k0 = e0 / M, k1 = e1 / M;
+            for (uint32_t i = k0 * LPW + tid; i < (k1 + 1) * LPW; i += nthr) {
+                const uint32_t k = i / LPW, tl = i - (i / LPW) * LPW;
+                const uint32_t e = k * M + lane0 + tl;
+                const uint4 w = win[k * LPW + tl];
+#pragma unroll
+                for (uint32_t j = 0; j < 4; j++) {
+                    const uint32_t p = 4 * e + j;
+                    if (p >= pos && p < pos + head) {
+                        const uint32_t v = sub(w, j);
+                        if constexpr (OUT == 0) out[p - pos] = v;
+                        else out[p - pos] = to_f32(v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const bool vec_ok = (head % 4) == 0 && ((uintptr_t)out % 16) == 0;
+        if (tid < LPW) {
+            for (uint64_t b = 0; b < nblocks; ++b) {
+                const uint64_t o0 = head + b * B;
+                OutT* ob = out + o0;
+                const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
+                uint4 c = win[(N - 2) * LPW + tid], d = win[(N - 1) * LPW + tid];
+                uint32_t o = 4u * (lane0 + tid);
+#pragma unroll 2
+                for (int k = 0; k < N - MM; ++k) {  // w_{k+m} still old
+                    const uint4 r = sfmt_next(win[k * LPW + tid], win[(k + MM) * LPW + tid], c, d);
+                    win[k * LPW + tid] = r;
+                    c = d;
+                    d = r;
+                    out_word(ob, o, lim, vec_ok, r);
+                    o += 4u * M;
+                }
+#pragma unroll 2
+                for (int k = N - MM; k < N; ++k) {  // w_{k+m} is new word k + m - N
+                    const uint4 r = sfmt_next(win[k * LPW + tid], win[(k + MM - N) * LPW + tid], c, d);
+                    win[k * LPW + tid] = r;
+                    c = d;
+                    d = r;
+                    out_word(ob, o, lim, vec_ok, r);
+                    o += 4u * M;
+                }
+            }
+        }
+        __syncthreads();
+        if (nblocks) {
+            for (int i = tid; i < N * LPW; i += nthr) {
+                const int k = i / LPW, t = i - (i / LPW) * LPW;
+                gwin[(size_t)k * M + lane0 + t] = win[k * LPW + t];
+            }
+        }
+        if (write_pos && tid == 0)
+            hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
+    }
+};
+
+template <int LPW, int OUT>
+__global__ __launch_bounds__(64) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len, int write_pos) {
+    using G = SfmtGen<LPW, OUT>;
+    __shared__ uint4 win[kSfmtN * LPW];
+    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
+}
+
+// Position after a call that emitted `len` elements, for launches with several
+// workgroups per state (none of them may touch the header while others read it).
+__global__ void finalize_gen_pos(uint8_t* state, uint64_t len) {
+    StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
+    const uint64_t B = hdr->block, pos = hdr->pos;
+    const uint64_t head = len < B - pos ? len : B - pos;
+    const uint64_t rest = len - head;
+    const uint64_t nblocks = (rest + B - 1) / B;
+    hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * B) : (uint32_t)(pos + head);
+}
+
+__global__ void reset_counter(uint32_t* c) { *c = 0; }
+
+// ---------------------------------------------------------------------------
+// Raw-sequence regeneration for the jump: rows of a lane-major buffer,
+// `src` -> `dst` (different buffers, so there is no read/write hazard).
+// ---------------------------------------------------------------------------
+
+template <class P>
+__device__ void raw_twist_rows(const typename P::W* src, typename P::W* dst, int rows, int stride, int tid, int nthr) {
+    using W = typename P::W;
+    constexpr int N = P::N, MM = P::MM, D = P::D;
+    for (int it = tid; it < rows * D; it += nthr) {
+        const int row = it / D, c = it - (it / D) * D;
+        const W* s = src + row * stride;
+        W* d = dst + row * stride;
+        const W n0 = twist(s[c], s[c + 1], s[c + MM]);
+        d[c] = n0;
+        const int r1 = c + D;
+        const W b1 = (r1 + 1 < N) ? s[r1 + 1] : twist(s[0], s[1], s[MM]);
+        const W n1 = twist(s[r1], b1, n0);
+        d[r1] = n1;
+        const int r2 = c + 2 * D;
+        if (r2 < N) {
+            const W b2 = (r2 + 1 < N) ? s[r2 + 1] : twist(s[0], s[1], s[MM]);
+            d[r2] = twist(s[r2], b2, n1);
+        }
+    }
+}
+
+struct SfmtRaw {
+    using W = uint4;
+    static constexpr int N = kSfmtN;
+};
+
+__device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int stride, int tid) {
+    if (tid >= rows) return;
+    const uint4* s = src + tid * stride;
+    uint4* d = dst + tid * stride;
+    uint4 c = s[kSfmtN - 2], e = s[kSfmtN - 1];
+    for (int k = 0; k < kSfmtN; ++k) {
+        const uint4 b = k < kSfmtN - kSfmtM ? s[k + kSfmtM] : d[k + kSfmtM - kSfmtN];
+        const uint4 r = sfmt_next(s[k], b, c, e);
+        d[k] = r;
+        c = e;
+        e = r;
+    }
+}
+
+__device__ __forceinline__ uint32_t xorw(uint32_t a, uint32_t b) { return a ^ b; }
+__device__ __forceinline__ uint64_t xorw(uint64_t a, uint64_t b) { return a ^ b; }
+__device__ __forceinline__ uint4 xorw(uint4 a, uint4 b) { return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w); }
+template <class W>
+__device__ __forceinline__ W zero_w() { return W(0); }
+template <>
+__device__ __forceinline__ uint4 zero_w<uint4>() { return make_uint4(0, 0, 0, 0); }
+
+// acc[s] ^= row[s0 + lane + 64 s] for every set coefficient i of poly with
+// window start s0 = k + i - b*N inside [0, N).
+template <class W, int N>
+__device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const W* row, const uint64_t* poly,
+                                                 int k, int b, int max_deg, int lane) {
+    constexpr int S = (N + 63) / 64;
+    int lo = b * N - k, hi = (b + 1) * N - k;  // coefficient range for this block
+    if (lo < 0) lo = 0;
+    if (hi > max_deg + 1) hi = max_deg + 1;
+    if (lo >= hi) return;
+    for (int wi = lo >> 6; wi <= (hi - 1) >> 6; ++wi) {
+        uint64_t bits = poly[wi];
+        const int base = wi * 64;
+        if (base < lo) bits &= ~0ull << (lo - base);
+        if (base + 64 > hi) bits &= (hi - base >= 64) ? ~0ull : ((1ull << (hi - base)) - 1);
+        while (bits) {
+            const int p = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const W* src = row + (k + base + p - b * N) + lane;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (s < S - 1 || lane + 64 * s < N) acc[s] = xorw(acc[s], src[64 * s]);
+        }
+    }
+}
+
+// ---- seeding (the base generators' published init_genrand / init_by_array;
+// the paper starts from a given state and leaves seeding open)
+__device__ void seed_mt32(uint32_t* x, const InitTask& t) {
+    if (t.kind == kSeedGenrand) {
+        x[0] = (uint32_t)t.seed;
+        for (uint32_t i = 1; i < 624; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+        return;
+    }
+    x[0] = 19650218u;
+    for (uint32_t i = 1; i < 624; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+    uint32_t i = 1, j = 0;
+    const uint32_t klen = t.key_len;
+    for (uint32_t s = (624 > klen ? 624 : klen); s; --s) {
+        x[i] = (x[i] ^ ((x[i - 1] ^ (x[i - 1] >> 30)) * 1664525u)) + t.key[j] + j;
+        if (++i >= 624) {
+            x[0] = x[623];
+            i = 1;
+        }
+        if (++j >= klen) j = 0;
+    }
+    for (uint32_t s = 623; s; --s) {
+        x[i] = (x[i] ^ ((x[i - 1] ^ (x[i - 1] >> 30)) * 1566083941u)) - i;
+        if (++i >= 624) {
+            x[0] = x[623];
+            i = 1;
+        }
+    }
+    x[0] = 0x80000000u;
+}
+__device__ void seed_mt64(uint64_t* x, const InitTask& t) {
+    x[0] = t.seed;
+    for (uint64_t i = 1; i < 312; i++) x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + i;
+}
+__device__ void seed_sfmt(uint4* w, const InitTask& t) {
+    uint32_t* x = reinterpret_cast<uint32_t*>(w);
+    x[0] = (uint32_t)t.seed;
+    for (uint32_t i = 1; i < 624; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+    // period certification with the SFMT19937 parity vector (1, 0, 0, 0x13c9e684)
+    const uint32_t inner = (x[0] & 1u) ^ (x[3] & 0x13c9e684u);
+    if ((__builtin_popcount(inner) & 1) == 0) x[0] ^= 1u;
+}
+
+template <class W>
+__device__ void seed_state(W* x, const InitTask& t);
+template <>
+__device__ void seed_state<uint32_t>(uint32_t* x, const InitTask& t) { seed_mt32(x, t); }
+template <>
+__device__ void seed_state<uint64_t>(uint64_t* x, const InitTask& t) { seed_mt64(x, t); }
+template <>
+__device__ void seed_state<uint4>(uint4* x, const InitTask& t) { seed_sfmt(x, t); }
+
+template <class W, int N>
+__device__ void twist_rows(const W* src, W* dst, int rows, int stride, int tid, int nthr);
+template <>
+__device__ void twist_rows<uint32_t, 624>(const uint32_t* s, uint32_t* d, int rows, int stride, int tid, int nthr) {
+    raw_twist_rows<MT32P>(s, d, rows, stride, tid, nthr);
+}
+template <>
+__device__ void twist_rows<uint64_t, 312>(const uint64_t* s, uint64_t* d, int rows, int stride, int tid, int nthr) {
+    raw_twist_rows<MT64P>(s, d, rows, stride, tid, nthr);
+}
+template <>
+__device__ void twist_rows<uint4, 156>(const uint4* s, uint4* d, int rows, int stride, int tid, int) {
+    raw_twist_rows_sfmt(s, d, rows, stride, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Init and jump. G lanes per workgroup, one wavefront per lane.
+//   init: the raw sequence is the seeded base generator's (one shared row),
+//         lane t uses polynomial slot t, offset k = N (start one block in).
+//   jump: each lane regenerates its own row from its window, all lanes use
+//         the same polynomial, offset k = pos / M (whole words consumed).
+// Buffer: rows of 2N words (lower = block b, upper = block b + 1).
+// ---------------------------------------------------------------------------
+
+template <class W, int N, int G, bool INIT>
+__device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* poly, uint32_t lane_stride,
+                        int max_deg, int k, const InitTask* init, W* buf) {
+    constexpr int S = (N + 63) / 64;
+    constexpr int ROWS = INIT ? 1 : G;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // lane of the group handled by this wave
+    state = uniform(state);
+    poly = uniform(poly);
+    k = (int)uniform((uint32_t)k);
+    max_deg = (int)uniform((uint32_t)max_deg);
+    M = uniform(M);
+    W* gwin = reinterpret_cast<W*>(state + kHeaderBytes);
+    const uint32_t lane0 = g * G;
+
+    if constexpr (INIT) {
+        if (tid == 0) seed_state<W>(buf, *init);
+    } else {
+        for (int i = tid; i < N * G; i += nthr) {
+            const int j = i / G, r = i - (i / G) * G;
+            buf[r * 2 * N + j] = gwin[(size_t)j * M + lane0 + r];
+        }
+    }
+    __syncthreads();
+    twist_rows<W, N>(buf, buf + N, ROWS, 2 * N, tid, nthr);
+    __syncthreads();
+
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    const uint64_t* mypoly = poly + (size_t)lane_stride * (lane0 + w);
+    const W* myrow = buf + (INIT ? 0 : w * 2 * N);
+    const int last_b = (k + max_deg) / N;
+    for (int b = 0; b <= last_b; ++b) {
+        if (w < G) accumulate_block<W, N>(acc, myrow, mypoly, k, b, max_deg, lane);
+        if (b == last_b) break;
+        __syncthreads();
+        for (int i = tid; i < ROWS * N; i += nthr) {  // upper -> lower
+            const int r = i / N, j = i - (i / N) * N;
+            buf[r * 2 * N + j] = buf[r * 2 * N + N + j];
+        }
+        __syncthreads();
+        twist_rows<W, N>(buf, buf + N, ROWS, 2 * N, tid, nthr);
+        __syncthreads();
+    }
+    __syncthreads();
+    // stage as [j][lane] and store rows of G contiguous words
+    if (w < G) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = lane + 64 * s;
+            if (j < N) buf[j * G + w] = acc[s];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < N * G; i += nthr) {
+        const int j = i / G, r = i - (i / G) * G;
+        gwin[(size_t)j * M + lane0 + r] = buf[i];
+    }
+}
+
+template <class W, int N, int G>
+__global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, InitTask one, uint32_t M,
+                                                      const uint64_t* lane_polys, uint32_t max_deg, uint32_t variant) {
+    constexpr int BUF = (2 * N > N * G) ? 2 * N : N * G;
+    __shared__ __attribute__((aligned(16))) W buf[BUF];
+    const uint32_t groups = M / G;
+    const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
+    const InitTask task = tasks ? tasks[ti] : one;
+    dephase<W, N, G, true>(task.state, M, g, lane_polys, kPolyWords, (int)max_deg, N, &task, buf);
+    if (g == 0 && threadIdx.x == 0) {
+        StateHeader* h = reinterpret_cast<StateHeader*>(task.state);
+        h->magic = kMagic;
+        h->version = kVersion;
+        h->variant = variant;
+        h->M = M;
+        h->n = N;
+        h->word_bytes = sizeof(W);
+        h->block = (uint32_t)(N * M * (sizeof(W) == 16 ? 4 : 1));
+        h->pos = 0;
+    }
+}
+
+template <class W, int N, int G>
+__global__ __launch_bounds__(G * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
+    __shared__ __attribute__((aligned(16))) W buf[2 * N * G];
+    const uint32_t groups = M / G;
+    const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
+    const JumpTask task = tasks ? tasks[ti] : one;
+    const StateHeader* h = reinterpret_cast<const StateHeader*>(task.state);
+    const uint32_t per = sizeof(W) == 16 ? 4u : 1u;
+    const int k = (int)(h->pos / (per * M));  // words of every lane already consumed
+    dephase<W, N, G, false>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k, nullptr, buf);
+}
+
+__global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    StateHeader* h = reinterpret_cast<StateHeader*>(tasks ? tasks[i].state : one.state);
+    const uint32_t per = h->word_bytes == 16 ? 4u : 1u;
+    h->pos = h->pos % (per * h->M);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+static int lanes_per_group(uint32_t variant, uint32_t M) {
+    // one wavefront per lane; at most 16 lanes (1024 threads) per workgroup
+    (void)variant;
+    return M < 16 ? (int)M : 16;
+}
+
+#define VMT_G_SWITCH(G, ...)                                 \
+    switch (G) {                                             \
+        case 1: { constexpr int GG = 1; __VA_ARGS__; break; } \
+        case 2: { constexpr int GG = 2; __VA_ARGS__; break; } \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; break; } \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; break; } \
+        default: { constexpr int GG = 16; __VA_ARGS__; break; } \
+    }
+
+hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, const InitTask& one, uint32_t count,
+                       const uint64_t* d_lane_polys, uint32_t max_deg, hipStream_t stream) {
+    const int G = lanes_per_group(variant, M);
+    const dim3 grid(count * (M / G)), block(G * 64);
+    if (variant == kMT32) {
+        VMT_G_SWITCH(G, init_kernel<uint32_t, 624, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant))
+    } else if (variant == kMT64) {
+        VMT_G_SWITCH(G, init_kernel<uint64_t, 312, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant))
+    } else {
+        VMT_G_SWITCH(G, init_kernel<uint4, 156, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant))
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
+                       hipStream_t stream) {
+    // 2N*G words per workgroup stay within 40 KB of LDS
+    int G = lanes_per_group(variant, M);
+    if (variant == kMT32 && G > 8) G = 8;
+    if (variant == kMT64 && G > 8) G = 8;
+    if (variant == kSFMT && G > 4) G = 4;
+    const dim3 grid(count * (M / G)), block(G * 64);
+    if (variant == kMT32) {
+        VMT_G_SWITCH(G, jump_kernel<uint32_t, 624, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
+    } else if (variant == kMT64) {
+        VMT_G_SWITCH(G, jump_kernel<uint64_t, 312, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
+    } else {
+        VMT_G_SWITCH(G, jump_kernel<uint4, 156, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    finalize_jump_pos<<<(count + 255) / 256, 256, 0, stream>>>(d_tasks, one, count);
+    return hipGetLastError();
+}
+
+
+bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind) {
+    if (lpw == 0 || lpw > 16 || (lpw & (lpw - 1)) || M % lpw) return false;
+    if (variant == kMT32) return out_kind == kOutU32 || out_kind == kOutF32;
+    if (variant == kMT64) return out_kind == kOutU64 || out_kind == kOutF64 || out_kind == kOutF32;
+    return out_kind == kOutU32 || out_kind == kOutF32;
+}
+
+#define VMT_LPW_SWITCH(L, ...)                                \
+    switch (L) {                                              \
+        case 1: { constexpr int LL = 1; __VA_ARGS__; break; }  \
+        case 2: { constexpr int LL = 2; __VA_ARGS__; break; }  \
+        case 4: { constexpr int LL = 4; __VA_ARGS__; break; }  \
+        case 8: { constexpr int LL = 8; __VA_ARGS__; break; }  \
+        default: { constexpr int LL = 16; __VA_ARGS__; break; } \
+    }
+
+hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state, void* d_out,
+                           uint64_t len, hipStream_t stream) {
+    const dim3 grid(M / lpw);
+    const int wp = (lpw == M) ? 1 : 0;
+    if (variant == kMT32) {
+        if (out_kind == kOutU32) {
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+        } else {
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+        }
+    } else if (variant == kMT64) {
+        if (out_kind == kOutU64) {
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+        } else if (out_kind == kOutF64) {
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+        } else {
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+        }
+    } else {
+        const dim3 block(64);
+        if (out_kind == kOutU32) {
+            VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<LL, 0><<<grid, block, 0, stream>>>(d_state, d_out, len, wp))
+        } else {
+            VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<LL, 1><<<grid, block, 0, stream>>>(d_state, d_out, len, wp))
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || wp) return e;
+    finalize_gen_pos<<<1, 1, 0, stream>>>(d_state, len);
+    return hipGetLastError();
+}
+
+bool batch_supported(uint32_t variant, uint32_t M, int out_kind) {
+    if (variant == kSFMT) return false;
+    return generate_supported(variant, M, M, out_kind);
+}
+
+template <class K>
+static uint32_t grid_for(K kernel, int threads, int device) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+    return (uint32_t)(per_cu * cus);
+}
+
+#define VMT_BATCH_KERNEL(P, OUTK)                                                                  \
+    VMT_LPW_SWITCH(M, kern = reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK>); \
+                   threads = mt_threads<P, LL>())
+
+static const void* batch_kernel_ptr(uint32_t variant, uint32_t M, int out_kind, int* threads_out) {
+    const void* kern = nullptr;
+    int threads = 0;
+    if (variant == kMT32) {
+        if (out_kind == kOutU32) { VMT_BATCH_KERNEL(MT32P, 0) }
+        else { VMT_BATCH_KERNEL(MT32P, 1) }
+    } else {
+        if (out_kind == kOutU64) { VMT_BATCH_KERNEL(MT64P, 0) }
+        else if (out_kind == kOutF64) { VMT_BATCH_KERNEL(MT64P, 2) }
+        else { VMT_BATCH_KERNEL(MT64P, 1) }
+    }
+    *threads_out = threads;
+    return kern;
+}
+
+uint32_t batch_grid(uint32_t variant, uint32_t M, int out_kind, int device) {
+    int threads = 0;
+    const void* kern = batch_kernel_ptr(variant, M, out_kind, &threads);
+    return grid_for(kern, threads, device);
+}
+
+hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
+                        uint32_t* d_counter, uint32_t grid, hipStream_t stream) {
+    reset_counter<<<1, 1, 0, stream>>>(d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (grid > count) grid = count;
+    if (grid == 0) return hipSuccess;
+    int threads = 0;
+    const void* kern = batch_kernel_ptr(variant, M, out_kind, &threads);
+    void* args[] = {(void*)&d_tasks, (void*)&count, (void*)&d_counter};
+    return hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, stream);
+}
+
+}  // namespace vmt

@@ -1,0 +1,51 @@
+// vmt_launch.hpp -- host entry points into the HIP kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "vmt_common.hpp"
+
+namespace vmt {
+
+// Seeding kinds for InitTask.
+enum : uint32_t { kSeedGenrand = 0, kSeedByArray = 1 };
+
+struct InitTask {
+    uint8_t* state;
+    const uint32_t* key;  // device array (init_by_array)
+    uint64_t seed;        // init_genrand seed
+    uint32_t kind;
+    uint32_t key_len;
+};
+
+// Output kinds (same values as VMT_OUT_*).
+enum : int { kOutU32 = 0, kOutU64 = 1, kOutF32 = 2, kOutF64 = 3 };
+
+// Seed and de-phase `count` states: lane t of state i = X_0(i) advanced by
+// t*J. lane_polys holds M slots of kPolyWords words (slot t = t^(tJ) mod mu).
+// With d_tasks == nullptr the single task `one` (passed by value) is used.
+hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, const InitTask& one, uint32_t count,
+                       const uint64_t* d_lane_polys, uint32_t max_deg, hipStream_t stream);
+
+// Jump `count` states (all of one variant and M), then fix their positions.
+hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
+                       hipStream_t stream);
+
+// Generate `len` elements from one state into d_out with `lpw` lanes per
+// workgroup (lpw divides M; lpw == M uses one workgroup).
+hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state,
+                           void* d_out, uint64_t len, hipStream_t stream);
+
+// Persistent batched generation; d_counter (one uint32) is reset on the
+// stream before the launch.
+hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
+                        uint32_t* d_counter, uint32_t grid, hipStream_t stream);
+
+// Whether the combination is compiled in, and the persistent grid size.
+bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind);
+bool batch_supported(uint32_t variant, uint32_t M, int out_kind);
+uint32_t batch_grid(uint32_t variant, uint32_t M, int out_kind, int device);
+
+}  // namespace vmt

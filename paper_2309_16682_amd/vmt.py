@@ -1,0 +1,293 @@
+"""Thin Python binding of libvmt (include/vmt.h), argument marshalling only.
+
+Every function has the name of its C counterpart and forwards to it; device
+buffers are torch tensors on a ROCm device (their data_ptr is passed), streams
+are torch streams (None = the current stream). All generation, seeding and
+jump work runs in the library's HIP kernels: if libvmt.so is missing or the
+GPU is absent the calls raise, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvmt.so")
+
+VMT_OK = 0
+VMT_EINVAL, VMT_EVARIANT, VMT_ENOMEM, VMT_EDEVICE, VMT_EBUSY, VMT_ESTATE = -1, -2, -3, -4, -5, -6
+VMT_MT32, VMT_MT64, VMT_SFMT = 0, 1, 2
+VMT_OUT_U32, VMT_OUT_U64, VMT_OUT_F32, VMT_OUT_F64 = 0, 1, 2, 3
+
+STATE_WORDS = {VMT_MT32: 624, VMT_MT64: 312, VMT_SFMT: 156}
+
+
+class VmtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vmt error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libvmt.so (built by python -m paper_2309_16682_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2309_16682_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, U32, U64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    IP = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "vmt_last_error": ([], ctypes.c_char_p),
+        "vmt_version": ([], ctypes.c_char_p),
+        "vmt_ctx_create": ([I, IP], P),
+        "vmt_ctx_destroy": ([P], I),
+        "vmt_state_bytes": ([I, U32], SZ),
+        "vmt_init_genrand": ([P, I, U64, U32, P, P], I),
+        "vmt_init_by_array": ([P, I, P, SZ, U32, P, P], I),
+        "vmt_init_by_array_batch": ([P, P, SZ, SZ, U32, P, P], I),
+        "vmt_jump": ([P, P, P, SZ, P], I),
+        "vmt_jump_pow2": ([P, P, U32, P], I),
+        "vmt_jump_pow2_batch": ([P, P, P, SZ, P], I),
+        "vmt_generate_u32": ([P, P, SZ, P, P], I),
+        "vmt_generate_u64": ([P, P, SZ, P, P], I),
+        "vmt_uniform_f32": ([P, P, SZ, P, P], I),
+        "vmt_uniform_f64": ([P, P, SZ, P, P], I),
+        "vmt_batch_generate": ([P, P, P, P, SZ, I, P], I),
+        "vmt_batch_plan_create": ([P, P, P, P, SZ, I, IP], P),
+        "vmt_batch_plan_launch": ([P, P], I),
+        "vmt_batch_plan_destroy": ([P], I),
+        "vmt_state_export": ([P, P, P, SZ, P], I),
+        "vmt_state_import": ([P, P, P, SZ, P], I),
+        "vmt_state_release": ([P, P], I),
+        "vmt_minpoly": ([P, I, P, SZ, IP], I),
+        "vmt_jump_poly": ([P, I, P, SZ, P, SZ, IP], I),
+        "vmt_set_tuning": ([P, I, U32, U32], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def exported_symbols() -> list:
+    return [
+        "vmt_last_error", "vmt_version", "vmt_ctx_create", "vmt_ctx_destroy", "vmt_state_bytes",
+        "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
+        "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
+        "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
+        "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_set_tuning",
+    ]
+
+
+def _check(code: int) -> int:
+    if code != VMT_OK:
+        raise VmtError(code, lib().vmt_last_error().decode())
+    return code
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u64_words(d: int):
+    if d < 0:
+        raise ValueError("distance must be non-negative")
+    nw = max(1, (d.bit_length() + 63) // 64)
+    arr = (ctypes.c_uint64 * nw)(*[(d >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(nw)])
+    return arr, nw
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
+
+
+# ---- C API, one Python function per C function ---------------------------------
+
+
+def vmt_version() -> str:
+    return lib().vmt_version().decode()
+
+
+def vmt_ctx_create(device: int = 0):
+    st = ctypes.c_int(0)
+    h = lib().vmt_ctx_create(device, ctypes.byref(st))
+    if not h:
+        raise VmtError(st.value, lib().vmt_last_error().decode())
+    return h
+
+
+def vmt_ctx_destroy(ctx) -> None:
+    _check(lib().vmt_ctx_destroy(ctx))
+
+
+def vmt_state_bytes(variant: int, M: int) -> int:
+    return int(lib().vmt_state_bytes(variant, M))
+
+
+def vmt_init_genrand(ctx, variant, seed, M, d_state, stream=None):
+    return _check(lib().vmt_init_genrand(ctx, variant, seed, M, _dptr(d_state), _stream(stream)))
+
+
+def vmt_init_by_array(ctx, variant, key, M, d_state, stream=None):
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    return _check(
+        lib().vmt_init_by_array(ctx, variant, k.ctypes.data_as(ctypes.c_void_p), k.size, M, _dptr(d_state), _stream(stream))
+    )
+
+
+def vmt_init_by_array_batch(ctx, keys, M, d_states, stream=None):
+    """keys: uint32 array of shape (count, key_len); d_states: list of tensors."""
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    assert k.ndim == 2 and k.shape[0] == len(d_states)
+    ptrs = _ptr_array([s.data_ptr() for s in d_states])
+    return _check(
+        lib().vmt_init_by_array_batch(
+            ctx, k.ctypes.data_as(ctypes.c_void_p), k.shape[1], k.shape[0], M, ptrs, _stream(stream)
+        )
+    )
+
+
+def vmt_jump(ctx, d_state, distance: int, stream=None):
+    arr, nw = _u64_words(distance)
+    return _check(lib().vmt_jump(ctx, _dptr(d_state), arr, nw, _stream(stream)))
+
+
+def vmt_jump_pow2(ctx, d_state, k: int, stream=None):
+    return _check(lib().vmt_jump_pow2(ctx, _dptr(d_state), k, _stream(stream)))
+
+
+def vmt_jump_pow2_batch(ctx, d_states, ks, stream=None):
+    kk = np.ascontiguousarray(ks, dtype=np.uint32)
+    ptrs = _ptr_array([s.data_ptr() for s in d_states])
+    return _check(lib().vmt_jump_pow2_batch(ctx, ptrs, kk.ctypes.data_as(ctypes.c_void_p), kk.size, _stream(stream)))
+
+
+def vmt_generate_u32(ctx, d_state, n, d_out, stream=None):
+    return _check(lib().vmt_generate_u32(ctx, _dptr(d_state), n, _dptr(d_out), _stream(stream)))
+
+
+def vmt_generate_u64(ctx, d_state, n, d_out, stream=None):
+    return _check(lib().vmt_generate_u64(ctx, _dptr(d_state), n, _dptr(d_out), _stream(stream)))
+
+
+def vmt_uniform_f32(ctx, d_state, n, d_out, stream=None):
+    return _check(lib().vmt_uniform_f32(ctx, _dptr(d_state), n, _dptr(d_out), _stream(stream)))
+
+
+def vmt_uniform_f64(ctx, d_state, n, d_out, stream=None):
+    return _check(lib().vmt_uniform_f64(ctx, _dptr(d_state), n, _dptr(d_out), _stream(stream)))
+
+
+def vmt_batch_generate(ctx, d_states, lens, d_outs, out_kind, stream=None):
+    """d_states: list of state tensors (or raw device addresses); d_outs: list
+    of output tensors / addresses; lens: element counts."""
+    n = len(d_states)
+    sp = _ptr_array([s if isinstance(s, int) else s.data_ptr() for s in d_states])
+    op = _ptr_array([o if isinstance(o, int) else o.data_ptr() for o in d_outs])
+    ln = np.ascontiguousarray(lens, dtype=np.uint64)
+    return _check(
+        lib().vmt_batch_generate(ctx, sp, ln.ctypes.data_as(ctypes.c_void_p), op, n, out_kind, _stream(stream))
+    )
+
+
+def vmt_batch_plan_create(ctx, d_states, lens, d_outs, out_kind):
+    n = len(d_states)
+    sp = _ptr_array([s if isinstance(s, int) else s.data_ptr() for s in d_states])
+    op = _ptr_array([o if isinstance(o, int) else o.data_ptr() for o in d_outs])
+    ln = np.ascontiguousarray(lens, dtype=np.uint64)
+    st = ctypes.c_int(0)
+    h = lib().vmt_batch_plan_create(ctx, sp, ln.ctypes.data_as(ctypes.c_void_p), op, n, out_kind, ctypes.byref(st))
+    if not h:
+        raise VmtError(st.value, lib().vmt_last_error().decode())
+    return h
+
+
+def vmt_batch_plan_launch(plan, stream=None):
+    return _check(lib().vmt_batch_plan_launch(plan, _stream(stream)))
+
+
+def vmt_batch_plan_destroy(plan):
+    return _check(lib().vmt_batch_plan_destroy(plan))
+
+
+def vmt_state_export(ctx, d_state, stream=None) -> np.ndarray:
+    buf = np.zeros(d_state.numel() * d_state.element_size(), dtype=np.uint8)
+    _check(lib().vmt_state_export(ctx, _dptr(d_state), buf.ctypes.data_as(ctypes.c_void_p), buf.size, _stream(stream)))
+    return buf
+
+
+def vmt_state_import(ctx, d_state, h_buf, stream=None):
+    b = np.ascontiguousarray(h_buf, dtype=np.uint8)
+    return _check(lib().vmt_state_import(ctx, _dptr(d_state), b.ctypes.data_as(ctypes.c_void_p), b.size, _stream(stream)))
+
+
+def vmt_state_release(ctx, d_state):
+    return _check(lib().vmt_state_release(ctx, _dptr(d_state)))
+
+
+def vmt_minpoly(ctx, variant) -> int:
+    out = np.zeros(400, np.uint64)
+    deg = ctypes.c_int(0)
+    _check(lib().vmt_minpoly(ctx, variant, out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(deg)))
+    return int.from_bytes(out.tobytes(), "little")
+
+
+def vmt_jump_poly(ctx, variant, distance: int) -> int:
+    arr, nw = _u64_words(distance)
+    out = np.zeros(400, np.uint64)
+    deg = ctypes.c_int(0)
+    _check(lib().vmt_jump_poly(ctx, variant, arr, nw, out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(deg)))
+    return int.from_bytes(out.tobytes(), "little")
+
+
+def vmt_set_tuning(ctx, variant, lanes_per_wg, threads=0):
+    return _check(lib().vmt_set_tuning(ctx, variant, lanes_per_wg, threads))
+
+
+# ---- small conveniences (still marshalling only) ---------------------------------
+
+
+def new_state(variant: int, M: int, device="cuda"):
+    """A device buffer of vmt_state_bytes(variant, M) bytes (uint8 tensor)."""
+    import torch
+
+    nbytes = vmt_state_bytes(variant, M)
+    if nbytes == 0:
+        raise ValueError("bad variant or M")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def header(state_bytes: np.ndarray) -> dict:
+    h = np.frombuffer(np.ascontiguousarray(state_bytes)[:32].tobytes(), dtype=np.uint32)
+    keys = ["magic", "version", "variant", "M", "n", "word_bytes", "block", "pos"]
+    return {k: int(v) for k, v in zip(keys, h)}
+
+
+def window(state_bytes: np.ndarray, variant: int, M: int) -> np.ndarray:
+    """The interleaved window of an exported state as (n, M) words
+    ((156, M, 4) uint32 for SFMT)."""
+    b = np.ascontiguousarray(state_bytes)[256:]
+    if variant == VMT_MT32:
+        return np.frombuffer(b.tobytes(), dtype=np.uint32).reshape(624, M)
+    if variant == VMT_MT64:
+        return np.frombuffer(b.tobytes(), dtype=np.uint64).reshape(312, M)
+    return np.frombuffer(b.tobytes(), dtype=np.uint32).reshape(156, M, 4)

@@ -1,0 +1,44 @@
+"""Shared helpers for the GPU parity tests: oracle references and device buffers."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import pyoracle as O
+from tests import golden_io
+
+VARIANT_NAMES = {0: "mt32", 1: "mt64", 2: "sfmt"}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_seed(variant, seed=None, key=None):
+    return O.seed_state(variant, seed=seed, key=key)
+
+
+def oracle_stream(variant, M, seed=None, key=None):
+    """Fresh oracle V-stream from init_genrand(seed) or init_by_array(key)."""
+    return O.VStream(variant, M, oracle_seed(variant, seed, key), golden_io.lane_poly(variant, M))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_prefix(variant, M, seed, count):
+    """First `count` elements of the V-stream (cached; read-only)."""
+    s = oracle_stream(variant, M, seed=seed).generate(count)
+    s.setflags(write=False)
+    return s
+
+
+def out_dtype(variant):
+    import torch
+
+    return torch.int32 if variant in (0, 2) else torch.int64
+
+
+def as_u(arr, variant):
+    """torch int tensor (cpu) -> numpy unsigned view."""
+    a = arr.numpy()
+    return a.view(np.uint32) if variant in (0, 2) else a.view(np.uint64)

@@ -1,0 +1,83 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and its host-side polynomial helpers agree with the oracle's fixtures."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests import golden_io
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vmt.h")).read()
+    return sorted(set(re.findall(r"\b(vmt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2309_16682_amd import vmt
+
+    lib = vmt.lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(vmt.exported_symbols()) == set(names)
+
+
+def test_host_only_context_and_error_paths():
+    from paper_2309_16682_amd import vmt
+
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        assert vmt.vmt_state_bytes(vmt.VMT_MT32, 16) == 256 + 624 * 16 * 4
+        assert vmt.vmt_state_bytes(vmt.VMT_MT64, 8) == 256 + 312 * 8 * 8
+        assert vmt.vmt_state_bytes(vmt.VMT_SFMT, 64) == 256 + 156 * 64 * 16
+        assert vmt.vmt_state_bytes(vmt.VMT_MT32, 3) == 0
+        assert vmt.vmt_state_bytes(7, 4) == 0
+        # device calls on a host-only context fail cleanly
+        r = vmt.lib().vmt_init_genrand(ctx, 0, 1, 4, ctypes.c_void_p(256), None)
+        assert r == vmt.VMT_EDEVICE
+        assert b"host-only" in vmt.lib().vmt_last_error()
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_library_minpoly_equals_oracle_fixture(variant):
+    from paper_2309_16682_amd import vmt
+
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        assert vmt.vmt_minpoly(ctx, variant) == golden_io.minpoly(variant)
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_library_lane_polynomials_equal_oracle_fixtures(variant):
+    from paper_2309_16682_amd import vmt
+
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        rows = golden_io.tpow2(variant)
+        for q in (19931, 19934, 19936):
+            assert vmt.vmt_jump_poly(ctx, variant, 1 << q) == rows[q]
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
+
+
+def test_library_jump_poly_small_distances_match_oracle():
+    from oracle import pyoracle as O
+    from paper_2309_16682_amd import vmt
+
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        for variant in (0, 1, 2):
+            mu = golden_io.minpoly(variant)
+            for d in (0, 1, 19936, 19937, 19968, 40000, 2**64 + 3, 3**50):
+                assert vmt.vmt_jump_poly(ctx, variant, d) == O.poly_powmod_t(d, mu), (variant, d)
+    finally:
+        vmt.vmt_ctx_destroy(ctx)

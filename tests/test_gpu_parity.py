@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element, bit-exact (integer outputs and exact float maps: tolerance 0)."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from tests import golden_io, stdpins
+from tests.gpu_helpers import as_u, oracle_prefix, oracle_stream, out_dtype, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_16682_amd import vmt  # noqa: E402
+
+MT32, MT64, SFMT = vmt.VMT_MT32, vmt.VMT_MT64, vmt.VMT_SFMT
+BLOCK = {MT32: 624, MT64: 312, SFMT: 156 * 4}  # stream elements per lane per block
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vmt.vmt_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    vmt.vmt_ctx_destroy(c)
+
+
+def gen(ctx, st, variant, n, kind="int"):
+    if kind == "int":
+        out = torch.empty(max(n, 1), dtype=out_dtype(variant), device="cuda")
+        if variant == MT64:
+            vmt.vmt_generate_u64(ctx, st, n, out)
+        else:
+            vmt.vmt_generate_u32(ctx, st, n, out)
+        torch.cuda.synchronize()
+        return as_u(out[:n].cpu(), variant)
+    if kind == "f32":
+        out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        vmt.vmt_uniform_f32(ctx, st, n, out)
+    else:
+        out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        vmt.vmt_uniform_f64(ctx, st, n, out)
+    torch.cuda.synchronize()
+    return out[:n].cpu().numpy()
+
+
+def new_init(ctx, variant, M, seed):
+    st = vmt.new_state(variant, M)
+    vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+    return st
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 1), (MT32, 2), (MT32, 4), (MT32, 8), (MT32, 16), (MT32, 32), (MT32, 64),
+                                       (MT64, 1), (MT64, 2), (MT64, 4), (MT64, 8), (MT64, 16), (MT64, 64),
+                                       (SFMT, 1), (SFMT, 2), (SFMT, 4), (SFMT, 16), (SFMT, 64)])
+def test_init_and_generate_matches_oracle(ctx, variant, M):
+    seed = 5489 if variant != SFMT else 1234
+    n = 3 * BLOCK[variant] * M + 7  # several blocks and a ragged tail
+    say(f"case init+generate variant={variant} M={M} n={n}")
+    st = new_init(ctx, variant, M, seed)
+    got = gen(ctx, st, variant, n)
+    ref = oracle_prefix(variant, M, seed, n)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4), (SFMT, 64)])
+def test_chunked_calls_equal_one_stream(ctx, variant, M):
+    seed = 99
+    rng = np.random.default_rng(7)
+    B = BLOCK[variant] * M
+    sizes = [0, 1, 2, 3, B - 5, 1, B, B + 1, 5, 2 * B + 3, 17, 4 * B] + list(rng.integers(1, 3 * B, 6))
+    say(f"case chunked variant={variant} M={M} sizes={sizes}")
+    st = new_init(ctx, variant, M, seed)
+    parts = [gen(ctx, st, variant, int(s)) for s in sizes]
+    got = np.concatenate(parts)
+    ref = oracle_prefix(variant, M, seed, len(got))
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_mt32_config1_full_size_and_lane0_is_std_mt19937(ctx):
+    # V-MT19937-32, M = 16, init_genrand(5489), 2^24 uint32 in one call
+    n = 1 << 24
+    say("case mt32 M=16 n=2^24")
+    st = new_init(ctx, MT32, 16, 5489)
+    got = gen(ctx, st, MT32, n)
+    np.testing.assert_array_equal(got[0::16][:100000], stdpins.std_stream(32, 5489, 100000))
+    ref = oracle_stream(MT32, 16, seed=5489).generate(n)
+    np.testing.assert_array_equal(got, ref)
+    hdr = vmt.header(vmt.vmt_state_export(ctx, st))
+    assert hdr["pos"] == n - (n // 9984) * 9984  # 4096-element tail of the last block
+
+
+def test_mt64_config2_full_size_u64_and_f64(ctx):
+    # V-MT19937-64, M = 8, init_genrand(5489): 2^26 uint64, then f64 of the same stream
+    n = 1 << 26
+    say("case mt64 M=8 n=2^26 u64 + f64")
+    st = new_init(ctx, MT64, 8, 5489)
+    got = gen(ctx, st, MT64, n)
+    np.testing.assert_array_equal(got[0::8][:50000], stdpins.std_stream(64, 5489, 50000))
+    ref = oracle_stream(MT64, 8, seed=5489).generate(n)
+    np.testing.assert_array_equal(got, ref)
+    del got
+    st2 = new_init(ctx, MT64, 8, 5489)
+    f = gen(ctx, st2, MT64, n, "f64")
+    np.testing.assert_array_equal(f, O.map_f64(ref))
+    assert f.min() >= 0.0 and f.max() < 1.0
+
+
+@pytest.mark.parametrize("M", [4, 64])
+def test_sfmt_config3_full_size_u32_and_f32(ctx, M):
+    # V-SFMT19937, init(1234): 2^28 uint32, then f32 of the same stream
+    n = 1 << 28
+    say(f"case sfmt M={M} n=2^28 u32 + f32")
+    st = new_init(ctx, SFMT, M, 1234)
+    got = gen(ctx, st, SFMT, n)
+    ref = oracle_stream(SFMT, M, seed=1234).generate(n)
+    np.testing.assert_array_equal(got, ref)
+    del got
+    st2 = new_init(ctx, SFMT, M, 1234)
+    f = gen(ctx, st2, SFMT, n, "f32")
+    np.testing.assert_array_equal(f, O.map_f32(ref))
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT32, 4), (MT64, 8), (SFMT, 4), (SFMT, 16)])
+def test_float_maps_match_oracle(ctx, variant, M):
+    n = 2 * BLOCK[variant] * M + 11
+    say(f"case f32 variant={variant} M={M}")
+    st = new_init(ctx, variant, M, 31337)
+    f = gen(ctx, st, variant, n, "f32")
+    ref = oracle_stream(variant, M, seed=31337).generate(n)
+    if variant == MT64:
+        exp = np.array([O.u64_to_f32(int(u)) for u in ref], dtype=np.float32)
+    else:
+        exp = O.map_f32(ref)
+    np.testing.assert_array_equal(f, exp)
+
+
+def test_f64_rejected_for_32bit_generators(ctx):
+    st = new_init(ctx, MT32, 4, 1)
+    out = torch.empty(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_uniform_f64(ctx, st, 10, out)
+    assert e.value.code == vmt.VMT_EVARIANT
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT32, 1), (MT64, 8), (MT64, 2), (SFMT, 4), (SFMT, 64)])
+@pytest.mark.parametrize("first", [0, 1, 13, "block-3", "block"])
+def test_jump_matches_oracle(ctx, variant, M, first):
+    mu = golden_io.minpoly(variant)
+    B = BLOCK[variant] * M
+    first = {"block-3": B - 3, "block": B}.get(first, first)
+    for d in (1, 5, 1000, 123457):
+        say(f"case jump variant={variant} M={M} first={first} d={d}")
+        st = new_init(ctx, variant, M, 2024)
+        ref = oracle_stream(variant, M, seed=2024)
+        a = gen(ctx, st, variant, first)
+        np.testing.assert_array_equal(a, ref.generate(first))
+        vmt.vmt_jump(ctx, st, d)
+        ref.jump(O.poly_powmod_t(d, mu))
+        np.testing.assert_array_equal(gen(ctx, st, variant, 2 * B + 9), ref.generate(2 * B + 9))
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4)])
+def test_jump_pow2_and_composition(ctx, variant, M):
+    mu = golden_io.minpoly(variant)
+    say(f"case jump_pow2 variant={variant} M={M}")
+    st = new_init(ctx, variant, M, 77)
+    ref = oracle_stream(variant, M, seed=77)
+    gen(ctx, st, variant, 101)
+    ref.generate(101)
+    for k in (0, 1, 32, 100, 256):
+        vmt.vmt_jump_pow2(ctx, st, k)
+        ref.jump(O.poly_sqr_chain(k, mu))
+        np.testing.assert_array_equal(gen(ctx, st, variant, 777), ref.generate(777))
+    # d1 then d2 equals d1 + d2
+    a = new_init(ctx, variant, M, 5)
+    b = new_init(ctx, variant, M, 5)
+    vmt.vmt_jump(ctx, a, 2**70 + 3)
+    vmt.vmt_jump(ctx, a, 999)
+    vmt.vmt_jump(ctx, b, 2**70 + 1002)
+    n = BLOCK[variant] * M + 5
+    np.testing.assert_array_equal(gen(ctx, a, variant, n), gen(ctx, b, variant, n))
+
+
+def test_init_by_array_matches_oracle(ctx):
+    key = np.array([0x123, 0x234, 0x345, 0x456], dtype=np.uint32)
+    for M in (1, 16):
+        say(f"case init_by_array M={M}")
+        st = vmt.new_state(MT32, M)
+        vmt.vmt_init_by_array(ctx, MT32, key, M, st)
+        n = 2 * 624 * M + 3
+        ref = oracle_stream(MT32, M, key=key).generate(n)
+        np.testing.assert_array_equal(gen(ctx, st, MT32, n), ref)
+
+
+def test_init_by_array_batch_matches_single(ctx):
+    from paper_2309_16682_amd.workload import batch_keys
+
+    keys = batch_keys(40, seed=42)
+    states = [vmt.new_state(MT32, 16) for _ in range(len(keys))]
+    say("case init_by_array_batch 40 states")
+    vmt.vmt_init_by_array_batch(ctx, keys, 16, states)
+    for i in (0, 17, 39):
+        ref = oracle_stream(MT32, 16, key=keys[i]).generate(20000)
+        np.testing.assert_array_equal(gen(ctx, states[i], MT32, 20000), ref)
+
+
+@pytest.mark.parametrize("variant,M,kind", [(MT32, 16, vmt.VMT_OUT_U32), (MT32, 4, vmt.VMT_OUT_F32),
+                                            (MT64, 8, vmt.VMT_OUT_U64), (MT64, 8, vmt.VMT_OUT_F64),
+                                            (MT64, 2, vmt.VMT_OUT_F32)])
+def test_batch_generate_matches_individual_streams(ctx, variant, M, kind):
+    rng = np.random.default_rng(3)
+    count = 48
+    B = BLOCK[variant] * M
+    lens = [0, 1, B - 1, B, B + 1] + list(rng.integers(1, 4 * B, count - 5))
+    say(f"case batch variant={variant} M={M} kind={kind} count={count}")
+    seeds = list(range(1000, 1000 + count))
+    states = [new_init(ctx, variant, M, s) for s in seeds]
+    # a different starting position per state
+    pre = [int(x) for x in rng.integers(0, B, count)]
+    for st, p in zip(states, pre):
+        gen(ctx, st, variant, p)
+    dt = {vmt.VMT_OUT_U32: torch.int32, vmt.VMT_OUT_U64: torch.int64, vmt.VMT_OUT_F32: torch.float32,
+          vmt.VMT_OUT_F64: torch.float64}[kind]
+    outs = [torch.empty(max(int(n), 1), dtype=dt, device="cuda") for n in lens]
+    for rep in range(2):  # twice: the second call continues every stream
+        vmt.vmt_batch_generate(ctx, states, lens, outs, kind)
+        torch.cuda.synchronize()
+        for i in range(count):
+            ref = oracle_stream(variant, M, seed=seeds[i])
+            ref.generate(pre[i] + rep * int(lens[i]))
+            r = ref.generate(int(lens[i]))
+            got = outs[i][: int(lens[i])].cpu().numpy()
+            if kind in (vmt.VMT_OUT_U32, vmt.VMT_OUT_U64):
+                got = as_u(outs[i][: int(lens[i])].cpu(), variant)
+                np.testing.assert_array_equal(got, r)
+            elif kind == vmt.VMT_OUT_F64:
+                np.testing.assert_array_equal(got, O.map_f64(r))
+            elif variant == MT64:
+                np.testing.assert_array_equal(got, np.array([O.u64_to_f32(int(u)) for u in r], np.float32))
+            else:
+                np.testing.assert_array_equal(got, O.map_f32(r))
+
+
+@pytest.mark.parametrize("variant,M,lpw", [(MT32, 16, 1), (MT32, 16, 4), (MT32, 64, 16), (MT64, 8, 2), (SFMT, 64, 4)])
+def test_split_lanes_over_workgroups(ctx, variant, M, lpw):
+    say(f"case split variant={variant} M={M} lpw={lpw}")
+    vmt.vmt_set_tuning(ctx, variant, lpw)
+    try:
+        st = new_init(ctx, variant, M, 8)
+        sizes = [5, BLOCK[variant] * M * 2 + 1, 3]
+        got = np.concatenate([gen(ctx, st, variant, s) for s in sizes])
+        np.testing.assert_array_equal(got, oracle_prefix(variant, M, 8, len(got)))
+    finally:
+        vmt.vmt_set_tuning(ctx, variant, 0)
+
+
+def test_export_import_resume(ctx):
+    say("case export/import")
+    st = new_init(ctx, MT64, 8, 11)
+    gen(ctx, st, MT64, 1234)
+    buf = vmt.vmt_state_export(ctx, st)
+    a = gen(ctx, st, MT64, 5000)
+    st2 = vmt.new_state(MT64, 8)
+    vmt.vmt_state_import(ctx, st2, buf)
+    np.testing.assert_array_equal(gen(ctx, st2, MT64, 5000), a)
+    bad = buf.copy()
+    bad[0] ^= 1
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_state_import(ctx, st2, bad)
+    assert e.value.code == vmt.VMT_ESTATE
+
+
+def test_unregistered_state_and_bad_arguments(ctx):
+    st = vmt.new_state(MT32, 4)
+    out = torch.empty(16, dtype=torch.int32, device="cuda")
+    fresh = vmt.vmt_ctx_create(0)  # empty registry: the address may be reused by torch
+    try:
+        with pytest.raises(vmt.VmtError) as e:
+            vmt.vmt_generate_u32(fresh, st, 16, out)
+        assert e.value.code == vmt.VMT_ESTATE
+    finally:
+        vmt.vmt_ctx_destroy(fresh)
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_init_genrand(ctx, MT32, 1, 3, st)
+    assert e.value.code == vmt.VMT_EINVAL
+    vmt.vmt_init_genrand(ctx, MT32, 1, 4, st)
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_generate_u64(ctx, st, 16, out)
+    assert e.value.code == vmt.VMT_EVARIANT
+    vmt.vmt_state_release(ctx, st)
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_generate_u32(ctx, st, 16, out)
+    assert e.value.code == vmt.VMT_ESTATE
+
+
+def test_state_window_after_init_is_first_twisted_block(ctx):
+    # lane t holds x_{tJ+n} .. x_{tJ+2n-1}: the oracle lane's next n raw words
+    for variant, M in ((MT32, 16), (MT64, 8), (SFMT, 4)):
+        st = new_init(ctx, variant, M, 5489)
+        buf = vmt.vmt_state_export(ctx, st)
+        hdr = vmt.header(buf)
+        assert hdr["pos"] == 0 and hdr["M"] == M and hdr["variant"] == variant
+        win = vmt.window(buf, variant, M)
+        ref = oracle_stream(variant, M, seed=5489)
+        for t in (0, M - 1):
+            lane = O.Scalar(variant, ref.lane_canon(t)).raw(O.STATE_WORDS[variant])
+            np.testing.assert_array_equal(win[:, t], lane)
