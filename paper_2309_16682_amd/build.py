@@ -51,7 +51,7 @@ def _run(cmd, verbose):
         print(out)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     gxx = shutil.which("g++") or "g++"
     inc = [f"-I{INCLUDE}", f"-I{CSRC}", f"-I{ROCM}/include"]
@@ -63,12 +63,13 @@ def build(verbose: bool = False) -> str:
             objs.append(obj)
         for src in HIP_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+            _run([hipcc, *HIP_FLAGS, *[f"-D{d}" for d in defines], *inc, "-c", os.path.join(CSRC, src), "-o", obj],
+                 verbose)
             objs.append(obj)
-        out_tmp = LIB + f".tmp{os.getpid()}"
+        out_tmp = out + f".tmp{os.getpid()}"
         _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs], verbose)
-        os.replace(out_tmp, LIB)
-    return LIB
+        os.replace(out_tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -212,6 +212,8 @@ uint32_t pick_lpw(vmt_ctx* ctx, int variant, uint32_t M) {
     return M < 16 ? M : 16;
 }
 
+size_t out_elem_bytes(int out_kind) { return out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64 ? 8 : 4; }
+
 int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, hipStream_t stream) {
     int st = set_device(ctx);
     if (st) return st;
@@ -223,6 +225,8 @@ int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, h
     }
     if (n == 0) return VMT_OK;
     if (!d_out) return fail(VMT_EINVAL, "null output");
+    if ((uintptr_t)d_out % out_elem_bytes(out_kind))
+        return fail(VMT_EINVAL, "output must be aligned to its element size");
     const uint32_t lpw = pick_lpw(ctx, info.variant, info.M);
     if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
         return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
@@ -305,8 +309,11 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
         if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
             return fail(VMT_EINVAL, "a state appears twice in one batch");
     }
-    for (size_t i = 0; i < count; i++)
+    for (size_t i = 0; i < count; i++) {
         if (lens[i] && !d_outs[i]) return fail(VMT_EINVAL, "null output for task %zu", i);
+        if ((uintptr_t)d_outs[i] % out_elem_bytes(out_kind))
+            return fail(VMT_EINVAL, "output %zu is not aligned to its element size", i);
+    }
     return VMT_OK;
 }
 
@@ -520,6 +527,7 @@ int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens
     vmt::BatchTask* d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
     uint32_t* d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
     e = hipMemcpyAsync(d_tasks, tasks.data(), bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = vmt::reset_counters(d_counter, stream);
     if (e == hipSuccess) {
         const uint32_t grid = vmt::batch_grid(info.variant, info.M, out_kind, ctx->device);
         e = vmt::launch_batch(info.variant, info.M, out_kind, d_tasks, (uint32_t)count, d_counter, grid, stream);
@@ -548,6 +556,8 @@ vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const
         return nullptr;
     }
     e = hipMemcpy(d_buf, tasks.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = vmt::reset_counters(reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256), nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(d_buf);
         if (status) *status = hip_fail(e, "hipMemcpy(plan)");

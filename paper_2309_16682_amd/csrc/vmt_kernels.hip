@@ -57,6 +57,10 @@ constexpr int kSfmtN = 156, kSfmtM = 122;
 __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, (unsigned char)0x78);
 }
+// (m & a) | (~m & b) in one VALU op (v_bitop3_b32, truth table 0xE4)
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, b, m, (unsigned char)0xE4);
+}
 // all ones if bit 0 of x is set
 __device__ __forceinline__ uint32_t lsb_mask(uint32_t x) { return (uint32_t)__builtin_amdgcn_sbfe((int)x, 0, 1); }
 
@@ -75,7 +79,7 @@ __device__ __forceinline__ T* uniform(T* p) {
 // ---- MT19937-32: eq. (step) with eq. (matmult); h = 0x80000000, l = 0x7fffffff.
 // omega = (x_k & h) | (x_{k+1} & l); bit 0 of omega is bit 0 of x_{k+1}.
 __device__ __forceinline__ uint32_t twist(uint32_t xk, uint32_t xk1, uint32_t xkm) {
-    const uint32_t omega = (xk & 0x80000000u) | (xk1 & 0x7fffffffu);
+    const uint32_t omega = select_bits(0x80000000u, xk, xk1);
     return xor_and(xkm ^ (omega >> 1), lsb_mask(xk1), 0x9908B0DFu);
 }
 // eq. (tempering), MT19937-32 constants; d = 0xFFFFFFFF needs no mask.
@@ -86,11 +90,45 @@ __device__ __forceinline__ uint32_t temper(uint32_t y) {
     return y ^ (y >> 18);
 }
 
+// Tempering of two MT19937-32 words held as one 64-bit register pair:
+// v_lshrrev_b64 / v_lshlrev_b64 shift both words at once (a 64-bit shift
+// issues at about 3/4 of the rate of a 32-bit one but does two words); the
+// bits that cross from one word into the other land exactly where the next
+// mask is zero (the masks b and c have no bits below 15 and 17), or are
+// cleared by the mask of the bitop3 that consumes them.
+__device__ __forceinline__ uint64_t pair64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+template <int S>
+__device__ __forceinline__ uint64_t shr64(uint64_t v) {
+    uint64_t r;
+    asm("v_lshrrev_b64 %0, %2, %1" : "=v"(r) : "v"(v), "n"(S));
+    return r;
+}
+template <int S>
+__device__ __forceinline__ uint64_t shl64(uint64_t v) {
+    uint64_t r;
+    asm("v_lshlrev_b64 %0, %2, %1" : "=v"(r) : "v"(v), "n"(S));
+    return r;
+}
+__device__ __forceinline__ void temper_pair(uint32_t& a, uint32_t& b) {
+    uint64_t s = shr64<11>(pair64(a, b));  // a: b's low 11 bits arrive in bits 21..31
+    a = xor_and(a, (uint32_t)s, 0x001FFFFFu);
+    b ^= (uint32_t)(s >> 32);
+    s = shl64<7>(pair64(a, b));  // b: a's top 7 bits arrive in bits 0..6, outside 0x9D2C5680
+    a = xor_and(a, (uint32_t)s, 0x9D2C5680u);
+    b = xor_and(b, (uint32_t)(s >> 32), 0x9D2C5680u);
+    s = shl64<15>(pair64(a, b));  // bits 0..14 of b, outside 0xEFC60000
+    a = xor_and(a, (uint32_t)s, 0xEFC60000u);
+    b = xor_and(b, (uint32_t)(s >> 32), 0xEFC60000u);
+    s = shr64<18>(pair64(a, b));  // a: bits 14..31 carry b's bits, keep 0..13
+    a = xor_and(a, (uint32_t)s, 0x00003FFFu);
+    b ^= (uint32_t)(s >> 32);
+}
+
 // ---- MT19937-64 on 32-bit halves (v_alignbit for the 64-bit shifts):
 // h = 0xFFFFFFFF80000000, l = 0x7FFFFFFF, a = 0xB5026F5AA96619E9.
 __device__ __forceinline__ uint64_t twist(uint64_t xk, uint64_t xk1, uint64_t xkm) {
     const uint32_t kh = (uint32_t)(xk >> 32), kl = (uint32_t)xk, k1 = (uint32_t)xk1;
-    const uint32_t ol = (kl & 0x80000000u) | (k1 & 0x7fffffffu);  // omega = (kh : ol)
+    const uint32_t ol = select_bits(0x80000000u, kl, k1);  // omega = (kh : ol)
     const uint32_t odd = lsb_mask(k1);
     const uint32_t lo = xor_and((uint32_t)xkm ^ __builtin_amdgcn_alignbit(kh, ol, 1), odd, 0xA96619E9u);
     const uint32_t hi = xor_and((uint32_t)(xkm >> 32) ^ (kh >> 1), odd, 0xB5026F5Au);
@@ -157,6 +195,44 @@ struct alignas(sizeof(T) * V) Vec {
     T v[V];
 };
 
+// Pointers that reach a kernel through memory (task lists, headers) are
+// generic; these accessors make the global address space explicit so the
+// compiler emits global_load/global_store (scalar base + 32-bit offset)
+// rather than flat accesses. The value travels as a vector of dwords (the
+// address-space cast is kept for vector types, not for aggregates).
+template <int NW>
+struct DwordVec {
+    typedef unsigned type __attribute__((ext_vector_type(NW)));
+};
+template <>
+struct DwordVec<1> {
+    typedef unsigned type;
+};
+#define VMT_GLOBAL __attribute__((address_space(1)))
+
+#ifndef VMT_NT_STORES
+#define VMT_NT_STORES 0
+#endif
+
+template <class T>
+__device__ __forceinline__ void gstore(T* p, const T& v) {
+    static_assert(sizeof(T) % 4 == 0 && sizeof(T) <= 16, "dword multiple");
+    using D = typename DwordVec<sizeof(T) / 4>::type;
+    D d;
+    __builtin_memcpy(&d, &v, sizeof(T));
+    if constexpr (VMT_NT_STORES) __builtin_nontemporal_store(d, (VMT_GLOBAL D*)p);
+    else *(VMT_GLOBAL D*)p = d;
+}
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+    static_assert(sizeof(T) % 4 == 0 && sizeof(T) <= 16, "dword multiple");
+    using D = typename DwordVec<sizeof(T) / 4>::type;
+    const D d = *(const VMT_GLOBAL D*)p;
+    T v;
+    __builtin_memcpy(&v, &d, sizeof(T));
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // MT generation: one workgroup owns LPW lanes (lanes g*LPW ...) of a state.
 // ---------------------------------------------------------------------------
@@ -180,11 +256,17 @@ struct MtGen {
     static constexpr int ITEMS = D * QPR;
     static constexpr int ITERS = (ITEMS + THREADS - 1) / THREADS;
     static constexpr bool THREE = N > 2 * D;  // MT19937-32 has a third index range
-    static constexpr size_t LDS_BYTES = sizeof(W) * N * LPW;
+    static constexpr int RANGES = THREE ? 3 : 2;
+    // The last word of a block, x_{n-1}, reads the new word 0 (its x_{k+1}
+    // wraps around). It belongs to column C_LAST, in range LAST_R.
+    static constexpr int LAST_R = RANGES - 1;
+    static constexpr int C_LAST = N - 1 - LAST_R * D;
+    static constexpr size_t LDS_BYTES = sizeof(W) * (N + 1) * LPW;  // window + new word 0
     using VW = Vec<W, V>;
     using Map = OutOf<OUT, W>;
     using OutT = typename Map::T;
-    using VO = Vec<OutT, V>;
+    static constexpr int CH = 16 / sizeof(OutT);  // output elements per 16-byte store
+    using VO = Vec<OutT, CH>;
 
     static __device__ __forceinline__ VW ld(const W* win, int row, int off) {
         return *reinterpret_cast<const VW*>(win + row * LPW + off);
@@ -198,28 +280,152 @@ struct MtGen {
         for (int j = 0; j < V; j++) r.v[j] = twist(a.v[j], b.v[j], m.v[j]);
         return r;
     }
-    // temper, map and store V lanes of one row at element index o (< lim)
-    static __device__ __forceinline__ void out_row(OutT* ob, uint32_t o, uint32_t lim, bool vec_ok, const VW& w) {
+    // CH consecutive window words -> tempered, mapped output chunk
+    static __device__ __forceinline__ VO temper_chunk(const W (&w)[CH]) {
         VO r;
+        if constexpr (sizeof(W) == 4 && OUT == 0) {
+            uint32_t t[CH];
 #pragma unroll
-        for (int j = 0; j < V; j++) r.v[j] = Map::map(temper(w.v[j]));
-        if (vec_ok && o + V <= lim) {
-            *reinterpret_cast<VO*>(ob + o) = r;
+            for (int j = 0; j < CH; j++) t[j] = w[j];
+#pragma unroll
+            for (int j = 0; j < CH; j += 2) temper_pair(t[j], t[j + 1]);
+#pragma unroll
+            for (int j = 0; j < CH; j++) r.v[j] = t[j];
         } else {
 #pragma unroll
-            for (int j = 0; j < V; j++)
-                if (o + j < lim) ob[o + j] = r.v[j];
+            for (int j = 0; j < CH; j++) r.v[j] = Map::map(temper(w[j]));
+        }
+        return r;
+    }
+
+    // Store phase, whole lanes (LPW == M): the window is the block in stream
+    // order, so window words [s_lo, s_hi) go to out[o_base ...] as 16-byte
+    // stores aligned to the *output*, whatever the start offset; at most
+    // CH - 1 elements at either end are stored one by one.
+    static __device__ __forceinline__ void store_contig(const W* win, OutT* out, uint32_t s_lo, uint32_t s_hi,
+                                                        uint64_t o_base, int tid) {
+        const uint32_t n = s_hi - s_lo;
+        OutT* ob = uniform(out + o_base);
+        const uint32_t mis = (uint32_t)(((uintptr_t)ob / sizeof(OutT)) % CH);
+        const uint32_t lead = mis ? (CH - mis < n ? CH - mis : n) : 0;  // elements before the first aligned chunk
+        const uint32_t nch = (n - lead) / CH;
+        const uint32_t tail0 = lead + nch * CH;
+        const uint32_t s0 = s_lo + lead;  // window index of the first chunk
+        constexpr int L = 16 / (int)sizeof(W) < CH ? 16 / (int)sizeof(W) : CH;  // words per 16-byte LDS read
+        if (s0 % CH == 0) {
+            for (uint32_t i = tid; i < nch; i += THREADS) {
+                W w[CH];
+                const uint32_t s = s0 + i * CH;
+#pragma unroll
+                for (int j = 0; j < CH; j += L) {
+                    const Vec<W, L> x = *reinterpret_cast<const Vec<W, L>*>(win + s + j);
+#pragma unroll
+                    for (int q = 0; q < L; q++) w[j + q] = x.v[q];
+                }
+                gstore(reinterpret_cast<VO*>(ob + lead + i * CH), temper_chunk(w));
+            }
+        } else {
+            for (uint32_t i = tid; i < nch; i += THREADS) {
+                W w[CH];
+                const uint32_t s = s0 + i * CH;
+#pragma unroll
+                for (int j = 0; j < CH; j++) w[j] = win[s + j];
+                gstore(reinterpret_cast<VO*>(ob + lead + i * CH), temper_chunk(w));
+            }
+        }
+        const uint32_t edge = lead + (n - tail0);
+        if ((uint32_t)tid < edge) {
+            const uint32_t e = (uint32_t)tid < lead ? tid : tail0 + (tid - lead);
+            gstore(ob + e, Map::map(temper(win[s_lo + e])));
         }
     }
 
+    // Store phase, lane subset (LPW < M): row k holds stream elements
+    // k*M + lane0 .. + LPW - 1; window words in [s_lo, s_hi) are stored.
+    static __device__ __forceinline__ void store_rows(const W* win, OutT* out, uint32_t s_lo, uint32_t s_hi,
+                                                      uint64_t o_base, uint32_t M, uint32_t lane0, int tid) {
+        OutT* ob = uniform(out + o_base);
+        const uint32_t k0 = s_lo / M, k1 = (s_hi - 1) / M;
+        constexpr int G = LPW >= CH ? CH : 1;  // elements per store
+        const bool vec = G == CH && ((uintptr_t)(ob + (int64_t)lane0 - (int64_t)s_lo) % 16) == 0;
+        for (uint32_t i = k0 * (LPW / G) + tid; i < (k1 + 1) * (LPW / G); i += THREADS) {
+            const uint32_t k = i / (LPW / G), tl = (i - k * (LPW / G)) * G;
+            const uint32_t e = k * M + lane0 + tl;  // stream position of the first element
+            if (vec && e >= s_lo && e + G <= s_hi) {
+                W w[CH];
+#pragma unroll
+                for (int j = 0; j < CH; j++) w[j] = win[k * LPW + tl + j];
+                gstore(reinterpret_cast<VO*>(ob + (e - s_lo)), temper_chunk(w));
+            } else {
+#pragma unroll
+                for (int j = 0; j < G; j++)
+                    if (e + j >= s_lo && e + j < s_hi) gstore(ob + (e + j - s_lo), Map::map(temper(win[k * LPW + tl + j])));
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void store(const W* win, OutT* out, uint32_t s_lo, uint32_t s_hi,
+                                                 uint64_t o_base, uint32_t M, uint32_t lane0, int tid) {
+        if (LPW == M) store_contig(win, out, s_lo, s_hi, o_base, tid);
+        else store_rows(win, out, s_lo, s_hi, o_base, M, lane0, tid);
+    }
+
+    // Twist one block in place: three index ranges per column, dependencies
+    // carried in registers; all reads before the first barrier, all writes
+    // after it.
+    static __device__ __forceinline__ void twist_block(W* win, int tid) {
+        W* x0new = win + N * LPW;  // new word 0 of every lane, for the last word
+        VW nw[ITERS][RANGES];
+        VW last_old[ITERS];
+#pragma unroll
+        for (int s = 0; s < ITERS; ++s) {
+            const int it = tid + s * THREADS;
+            if (it < ITEMS) {
+                const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
+                // range 1: old words only
+                const VW n0 = twistv(ld(win, c, off), ld(win, c + 1, off), ld(win, c + MM, off));
+                nw[s][0] = n0;
+                if (c == 0) st(x0new, 0, off, n0);
+                // range 2: x_{k+m-n} is the new word c
+                const int r1 = c + D;
+                if (THREE || c != C_LAST) nw[s][1] = twistv(ld(win, r1, off), ld(win, r1 + 1, off), n0);
+                else last_old[s] = ld(win, r1, off);
+                if constexpr (THREE) {
+                    // range 3: x_{k+m-n} is the new word c + D
+                    const int r2 = c + 2 * D;
+                    if (c < C_LAST) nw[s][2] = twistv(ld(win, r2, off), ld(win, r2 + 1, off), nw[s][1]);
+                    else if (c == C_LAST) last_old[s] = ld(win, r2, off);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the next column's loads from piling up
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < ITERS; ++s) {
+            const int it = tid + s * THREADS;
+            if (it < ITEMS) {
+                const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
+                st(win, c, off, nw[s][0]);
+                if (THREE || c != C_LAST) st(win, c + D, off, nw[s][1]);
+                if constexpr (THREE) {
+                    if (c < C_LAST) st(win, c + 2 * D, off, nw[s][2]);
+                }
+                if (c == C_LAST)  // x_{n-1}: reads the new word 0 published before the barrier
+                    st(win, N - 1, off, twistv(last_old[s], ld(x0new, 0, off), nw[s][LAST_R - 1]));
+            }
+        }
+        __syncthreads();
+    }
+
     // Emit `len` elements from `state` (lanes g*LPW .. g*LPW + LPW - 1).
-    static __device__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, W* win) {
+    static __device__ __forceinline__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos,
+                                               W* win) {
         state = uniform(state);
         out = uniform(out);
         len = uniform(len);
         StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
-        const uint32_t M = uniform(hdr->M);
-        const uint32_t pos = uniform(hdr->pos);
+        const uint32_t M = uniform(gload(&hdr->M));
+        const uint32_t pos = uniform(gload(&hdr->pos));
         W* gwin = reinterpret_cast<W*>(state + kHeaderBytes);
         const uint32_t B = (uint32_t)N * M;
         if (len == 0) return;
@@ -231,85 +437,25 @@ struct MtGen {
 
         for (int i = tid; i < N * QPR; i += THREADS) {
             const int k = i / QPR, q = i - (i / QPR) * QPR;
-            st(win, k, q * V, *reinterpret_cast<const VW*>(gwin + (size_t)k * M + lane0 + q * V));
+            st(win, k, q * V, gload(reinterpret_cast<const VW*>(gwin + (size_t)k * M + lane0 + q * V)));
         }
         __syncthreads();
-
-        if (head) {  // rest of the current block, tempered from the window
-            const uint32_t k0 = pos / M, k1 = (uint32_t)((pos + head - 1) / M);
-            for (uint32_t i = k0 * LPW + tid; i < (k1 + 1) * LPW; i += THREADS) {
-                const uint32_t k = i / LPW, tl = i - (i / LPW) * LPW;
-                const uint32_t e = k * M + lane0 + tl;
-                if (e >= pos && e < pos + head) out[e - pos] = Map::map(temper(win[k * LPW + tl]));
-            }
-        }
-
-        const bool vec_ok = (head % V) == 0 && ((uintptr_t)out % sizeof(VO)) == 0;
+        if (head) store(win, out, pos, pos + (uint32_t)head, 0, M, lane0, tid);  // rest of the current block
         for (uint64_t b = 0; b < nblocks; ++b) {
             const uint64_t o0 = head + b * B;
-            OutT* ob = out + o0;
-            const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
-            VW nw[ITERS][THREE ? 3 : 2];
-#pragma unroll
-            for (int s = 0; s < ITERS; ++s) {
-                const int it = tid + s * THREADS;
-                if (it < ITEMS) {
-                    const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
-                    const uint32_t oc = (uint32_t)c * M + lane0 + off;
-                    // range 1: old words only
-                    const VW n0 = twistv(ld(win, c, off), ld(win, c + 1, off), ld(win, c + MM, off));
-                    nw[s][0] = n0;
-                    out_row(ob, oc, lim, vec_ok, n0);
-                    // range 2: x_{k+m-n} is the new word c
-                    const int r1 = c + D;
-                    VW b1;
-                    if (THREE || r1 + 1 < N) {
-                        b1 = ld(win, r1 + 1, off);
-                    } else {  // last word of the block reads the new word 0
-                        b1 = twistv(ld(win, 0, off), ld(win, 1, off), ld(win, MM, off));
-                    }
-                    const VW n1 = twistv(ld(win, r1, off), b1, n0);
-                    nw[s][1] = n1;
-                    out_row(ob, oc + (uint32_t)D * M, lim, vec_ok, n1);
-                    if constexpr (THREE) {
-                        // range 3: x_{k+m-n} is the new word c + D
-                        const int r2 = c + 2 * D;
-                        if (r2 < N) {
-                            VW b2;
-                            if (r2 + 1 < N) b2 = ld(win, r2 + 1, off);
-                            else b2 = twistv(ld(win, 0, off), ld(win, 1, off), ld(win, MM, off));
-                            const VW n2 = twistv(ld(win, r2, off), b2, n1);
-                            nw[s][2] = n2;
-                            out_row(ob, oc + 2u * D * M, lim, vec_ok, n2);
-                        }
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);  // keep the next column's loads from piling up
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s = 0; s < ITERS; ++s) {
-                const int it = tid + s * THREADS;
-                if (it < ITEMS) {
-                    const int c = it / QPR, off = (it - (it / QPR) * QPR) * V;
-                    st(win, c, off, nw[s][0]);
-                    st(win, c + D, off, nw[s][1]);
-                    if constexpr (THREE) {
-                        if (c + 2 * D < N) st(win, c + 2 * D, off, nw[s][2]);
-                    }
-                }
-            }
-            __syncthreads();
+            twist_block(win, tid);
+            const uint32_t n = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
+            store(win, out, 0, n, o0, M, lane0, tid);
         }
-
         if (nblocks) {
+            __syncthreads();
             for (int i = tid; i < N * QPR; i += THREADS) {
                 const int k = i / QPR, q = i - (i / QPR) * QPR;
-                *reinterpret_cast<VW*>(gwin + (size_t)k * M + lane0 + q * V) = ld(win, k, q * V);
+                gstore(reinterpret_cast<VW*>(gwin + (size_t)k * M + lane0 + q * V), ld(win, k, q * V));
             }
         }
         if (write_pos && uniform((uint32_t)tid >> 6) == 0)  // wave 0, same value from every lane
-            hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
+            gstore(&hdr->pos, nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head));
     }
 };
 
@@ -317,26 +463,29 @@ template <class P, int LPW, int OUT>
 __global__ __launch_bounds__((mt_threads<P, LPW>())) void gen_mt_kernel(uint8_t* state, void* out, uint64_t len,
                                                                      int write_pos) {
     using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
-    __shared__ __attribute__((aligned(16))) typename P::W win[P::N * LPW];
+    __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LPW];
     G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
 }
 
 // Persistent batched generation: each workgroup pops states from a counter;
-// tasks are sorted longest first by the host.
+// tasks are sorted longest first by the host. counter[0] hands out tasks,
+// counter[1] counts finished workgroups; the last one to finish zeroes both,
+// so the next launch (or graph replay) starts from a clean counter.
 template <class P, int LANES, int OUT>
-__global__ __launch_bounds__((mt_threads<P, LANES>())) void batch_mt_kernel(const BatchTask* tasks, uint32_t count,
-                                                                         uint32_t* counter) {
+__global__ __launch_bounds__((mt_threads<P, LANES>()), 8) void batch_mt_kernel(const BatchTask* tasks, uint32_t count,
+                                                                            uint32_t* counter) {
     using G = MtGen<P, LANES, mt_threads<P, LANES>(), OUT>;
-    __shared__ __attribute__((aligned(16))) typename P::W win[P::N * LANES];
+    __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LANES];
     __shared__ uint32_t s_task;
     const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
     for (;;) {
         // Wave 0 takes a ticket without lane divergence (lane 0 adds 1, the
         // others 0): a lane-divergent branch next to the barriers of this loop
         // lets the compiler rotate the loop so that part of a wave re-enters
         // the barrier before the ticket is taken.
         if (wave == 0) {
-            const uint32_t mine = atomicAdd(counter, (threadIdx.x & 63) == 0 ? 1u : 0u);
+            const uint32_t mine = atomicAdd(counter, lane == 0 ? 1u : 0u);
             s_task = uniform(mine);
         }
         __syncthreads();
@@ -345,6 +494,13 @@ __global__ __launch_bounds__((mt_threads<P, LANES>())) void batch_mt_kernel(cons
         if (t >= count) break;
         const BatchTask task = tasks[t];
         G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, 0, true, win);
+    }
+    if (wave == 0) {
+        const uint32_t done = uniform(atomicAdd(counter + 1, lane == 0 ? 1u : 0u));
+        if (done == gridDim.x - 1 && lane == 0) {
+            counter[0] = 0;
+            counter[1] = 0;
+        }
     }
 }
 
@@ -378,7 +534,7 @@ struct SfmtGen {
         return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
     }
 
-    static __device__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, uint4* win) {
+    static __device__ __forceinline__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, uint4* win) {
         state = uniform(state);
         out = uniform(out);
         len = uniform(len);
@@ -477,7 +633,7 @@ __global__ void finalize_gen_pos(uint8_t* state, uint64_t len) {
     hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * B) : (uint32_t)(pos + head);
 }
 
-__global__ void reset_counter(uint32_t* c) { *c = 0; }
+__global__ void reset_counter(uint32_t* c) { c[threadIdx.x] = 0; }
 
 // ---------------------------------------------------------------------------
 // Raw-sequence regeneration for the jump: rows of a lane-major buffer,
@@ -881,11 +1037,13 @@ uint32_t batch_grid(uint32_t variant, uint32_t M, int out_kind, int device) {
     return grid_for(kern, threads, device);
 }
 
+hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream) {
+    reset_counter<<<1, 2, 0, stream>>>(d_counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
                         uint32_t* d_counter, uint32_t grid, hipStream_t stream) {
-    reset_counter<<<1, 1, 0, stream>>>(d_counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if (grid > count) grid = count;
     if (grid == 0) return hipSuccess;
     int threads = 0;

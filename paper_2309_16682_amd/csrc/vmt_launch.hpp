@@ -38,8 +38,9 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
 hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state,
                            void* d_out, uint64_t len, hipStream_t stream);
 
-// Persistent batched generation; d_counter (one uint32) is reset on the
-// stream before the launch.
+// Persistent batched generation. d_counter points to two uint32 that must be
+// zero before the first launch (reset_counters); every launch leaves them zero.
+hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream);
 hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
                         uint32_t* d_counter, uint32_t grid, hipStream_t stream);
 

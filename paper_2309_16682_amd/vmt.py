@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libvmt.so")
+# VMT_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("VMT_LIBRARY") or os.path.join(PKG, "libvmt.so")
 
 VMT_OK = 0
 VMT_EINVAL, VMT_EVARIANT, VMT_ENOMEM, VMT_EDEVICE, VMT_EBUSY, VMT_ESTATE = -1, -2, -3, -4, -5, -6
