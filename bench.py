@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--skip-secondary", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
     return ap.parse_args()
 
@@ -109,11 +111,73 @@ def cpu_baseline(seconds: float) -> dict:
     }
 
 
+def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chunk: int = 1 << 20) -> dict:
+    """Serving configuration: 4096 device-resident V-MT19937-64 (M = 8)
+    states seeded init_genrand(i + 1); Poisson arrivals at 20k requests/s,
+    request sizes log-uniform in [4 KiB, 256 MiB] of uint64, 10% of requests
+    a jump by 2^k with k uniform in [32, 256], 16 GiB admission budget. Requests
+    arriving in the first `warm` seconds run but are not counted."""
+    import torch
+
+    from paper_2309_16682_amd import vmt
+    from paper_2309_16682_amd.workload import serving_trace
+
+    n_states, Mv = 4096, 8
+    sb = vmt.vmt_state_bytes(vmt.VMT_MT64, Mv)
+    pool = torch.empty(n_states * sb, dtype=torch.uint8, device="cuda")
+    states = [pool[i * sb : (i + 1) * sb] for i in range(n_states)]
+    for i, st in enumerate(states):
+        vmt.vmt_init_genrand(ctx, vmt.VMT_MT64, i + 1, Mv, st)
+    torch.cuda.synchronize()
+    budget = 16 * 2**30
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    trace = serving_trace(seconds + warm, rate_per_s=20000.0, n_states=n_states, min_bytes=4096,
+                          max_bytes=256 << 20, elem_bytes=8, jump_fraction=0.1, kmin=32, kmax=256, seed=11)
+    reqs = [(r.t_arrival, r.state, 0 if r.kind == "gen" else 1, r.nelem if r.kind == "gen" else 0, r.k) for r in trace]
+    srv = vmt.vmt_server_create(ctx, states, arena, budget, budget, vmt.VMT_OUT_U64, n_streams=n_streams, mode=mode,
+                                chunk_elems=chunk)
+    try:
+        res, wall = vmt.vmt_server_run(srv, reqs, realtime=True)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    t_arr = np.array([r[0] for r in reqs])
+    kind = np.array([r[2] for r in reqs])
+    cnt = np.array([r[3] for r in reqs], dtype=np.float64)
+    ok = res["status"] == 0
+    counted = ok & (t_arr >= warm)
+    lat = (res["t_done"] - t_arr) * 1e3
+    wait = (res["t_admit"] - t_arr) * 1e3
+    g = counted & (kind == 0)
+    j = counted & (kind == 1)
+    gen_bytes = float((cnt[g] * 8).sum())
+    span = float(res["t_done"][counted].max() - warm)
+    out = {
+        "mode": "continuous batching" if mode == 0 else "plain (one launch per request)",
+        "chunk_elems": chunk,
+        "requests": int(counted.sum()),
+        "generate_requests": int(g.sum()),
+        "jump_requests": int(j.sum()),
+        "GB/s": round(gen_bytes / span / 1e9, 2),
+        "requests_per_s": round(float(counted.sum()) / span, 1),
+        "p50_ms": round(float(np.percentile(lat[g], 50)), 3),
+        "p99_ms": round(float(np.percentile(lat[g], 99)), 3),
+        "mean_ms": round(float(lat[g].mean()), 3),
+        "jump_p50_ms": round(float(np.percentile(lat[j], 50)), 3) if j.any() else None,
+        "jump_p99_ms": round(float(np.percentile(lat[j], 99)), 3) if j.any() else None,
+        "admit_wait_p99_ms": round(float(np.percentile(wait[counted], 99)), 3),
+        "launches": int(res["launch"].max() + 1),
+        "wall_s": round(wall, 2),
+    }
+    del arena, pool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(
-            f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+            f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
             "(independent generators shard across GPUs with no communication)",
             file=sys.stderr,
         )
@@ -268,7 +332,7 @@ def main():
     # ---- single-stream configurations (one generator each)
     if not args.skip_secondary:
         sec = {}
-        del arena
+        arena = None
         torch.cuda.empty_cache()
         for name, variant, M, seed, n, kind in (
             ("mt32_M16_2^24_u32", vmt.VMT_MT32, 16, 5489, 1 << 24, "u32"),
@@ -297,6 +361,20 @@ def main():
             log(f"{name}: {sec[name]}")
             del out
         result["single_stream"] = sec
+
+    arena = out_base = None  # the batch arena is not needed any more
+    torch.cuda.empty_cache()
+    if not args.skip_serving:
+        result["serving"] = {
+            "config": "4096 V-MT19937-64 (M=8) states, Poisson 20k req/s, log-uniform 4 KiB-256 MiB uint64, "
+            f"10% jumps by 2^k (k in [32,256]), 16 GiB budget, 4 streams, {args.serve_seconds:g} s after 1 s warm-up "
+            f"(plain: {max(args.serve_seconds / 10, 0.5):g} s after 0.2 s); batched tasks of at most 2^20 elements",
+            "batched": serving(ctx, args.serve_seconds, 1.0, 0),
+            "batched_unchunked": serving(ctx, args.serve_seconds, 1.0, 0, chunk=0),
+            # the plain form cannot keep up with the offered rate: a shorter trace keeps its run bounded
+            "plain": serving(ctx, max(args.serve_seconds / 10, 0.5), 0.2, 1, chunk=0),
+        }
+        log(f"serving: {result['serving']}")
 
     result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     log(f"cpu baseline: {result['cpu_baseline']['value']} GB/s")

@@ -158,6 +158,57 @@ int vmt_batch_plan_destroy(vmt_batch_plan* plan);
 int vmt_state_export(vmt_ctx* ctx, const void* d_state, void* h_buf, size_t bytes, hipStream_t stream);
 int vmt_state_import(vmt_ctx* ctx, void* d_state, const void* h_buf, size_t bytes, hipStream_t stream);
 
+/* ---- serving loop ------------------------------------------------------------
+ * A server owns S streams and serves requests against a fixed list of
+ * registered states (same variant and M) with outputs placed in a caller-owned
+ * device arena. Requests are admitted in arrival order while (a) each state has
+ * at most one request in flight, so a state's requests run in order, and (b)
+ * the outputs in flight fit in min(arena_bytes, budget_bytes). Mode 0
+ * (continuous batching): whenever a stream is free, everything admitted so far
+ * is launched on it as one persistent generation launch (longest first) and
+ * one jump launch; launches on different streams overlap. Mode 1 (plain): each
+ * admitted request is its own launch, streams taken round robin. Every task
+ * raises a completion flag in host memory, so outputs and states are released
+ * per request. The output of request i lives at d_arena + results[i].out_offset;
+ * by default later requests of the same run reuse the space of completed ones.
+ * Mode bit 1 (retain) places outputs one after another instead, so all outputs
+ * of a run stay in the arena (the budget still bounds the bytes in flight). */
+typedef struct {
+    double t_arrival; /* seconds from the start of the run */
+    uint32_t state;   /* index into the server's state list */
+    uint32_t kind;    /* 0: generate `count` elements, 1: jump by 2^k */
+    uint64_t count;
+    uint32_t k;
+    uint32_t reserved;
+} vmt_request;
+
+typedef struct {
+    double t_admit, t_launch, t_done; /* seconds from the start of the run (host clock) */
+    uint64_t out_offset;              /* byte offset of the output in the arena (generate) */
+    int32_t status;                   /* VMT_OK, or VMT_EINVAL for a request that cannot be served */
+    int32_t launch;                   /* index of the launch that ran it */
+} vmt_result;
+
+typedef struct vmt_server vmt_server;
+
+/* d_states: host array of n_states registered device states; d_arena:
+ * 256-byte aligned device memory; out_kind: VMT_OUT_* of the generated
+ * elements; 1 <= n_streams <= 16; mode: bit 0 plain launches, bit 1 retain.
+ * chunk_elems > 0 serves a generation request in tasks of at most that many
+ * elements, one per launch, back to back (the state stays reserved and the
+ * output space is held for the whole request), so that no launch is long
+ * and newly arrived requests are not queued behind large ones; 0 = one task. */
+vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_states, void* d_arena,
+                              size_t arena_bytes, uint64_t budget_bytes, int out_kind, uint32_t n_streams,
+                              int mode, uint64_t chunk_elems, int* status);
+/* Serve n requests. realtime = 1: request i becomes visible at its
+ * t_arrival (host clock from the start of the call); 0: all at once.
+ * results (host array of n) receives the timeline of each request; *wall_s
+ * the duration of the run. Blocks until every request has completed. */
+int vmt_server_run(vmt_server* server, const vmt_request* reqs, size_t n, vmt_result* results, int realtime,
+                   double* wall_s);
+int vmt_server_destroy(vmt_server* server);
+
 /* Forget a state: the context's registry is keyed by device address, so a
  * caller that frees a state's memory should release it first (a later
  * allocation at the same address must be initialised or imported again). */

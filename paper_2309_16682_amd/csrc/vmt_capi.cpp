@@ -21,6 +21,7 @@
 
 #include "gf2poly.hpp"
 #include "vmt_common.hpp"
+#include "vmt_internal.hpp"
 #include "vmt_launch.hpp"
 
 using vmt::Words;
@@ -262,7 +263,7 @@ int jump_with(vmt_ctx* ctx, void* d_state, const std::vector<uint64_t>& dist, co
         st = jump_table(ctx, info.variant, dist, known, &dp);
         if (st) return st;
     }
-    vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg};
+    vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
     hipError_t e = vmt::launch_jump(info.variant, info.M, nullptr, task, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "jump launch");
     return VMT_OK;
@@ -289,7 +290,7 @@ std::vector<vmt::BatchTask> batch_tasks(void* const* d_states, const uint64_t* l
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lens[a] > lens[b]; });
     std::vector<vmt::BatchTask> tasks;
     tasks.reserve(count);
-    for (uint32_t i : order) tasks.push_back(vmt::BatchTask{static_cast<uint8_t*>(d_states[i]), d_outs[i], lens[i]});
+    for (uint32_t i : order) tasks.push_back(vmt::BatchTask{static_cast<uint8_t*>(d_states[i]), d_outs[i], lens[i], nullptr});
     return tasks;
 }
 
@@ -318,6 +319,44 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
 }
 
 }  // namespace
+
+namespace vmt {
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ctx_state_info(vmt_ctx* ctx, const void* d_state, int* variant, uint32_t* M) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    StateInfo info;
+    int st = lookup(ctx, d_state, &info);
+    if (st) return st;
+    *variant = info.variant;
+    *M = info.M;
+    return VMT_OK;
+}
+
+int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly, uint32_t* degree) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const Words& g = pow2(ctx, variant, k);
+    DevPoly* dp = nullptr;
+    std::vector<uint64_t> key = {~0ull, k};
+    int st = jump_table(ctx, variant, key, &g, &dp);
+    if (st) return st;
+    *d_poly = dp->d;
+    *degree = dp->deg;
+    return VMT_OK;
+}
+
+int ctx_device(vmt_ctx* ctx) { return ctx->device; }
+
+}  // namespace vmt
 
 extern "C" {
 
@@ -486,7 +525,7 @@ int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks,
             std::vector<uint64_t> key = {~0ull, ks[i]};
             st = jump_table(ctx, info.variant, key, &g, &dp);
             if (st) return st;
-            tasks[i] = vmt::JumpTask{static_cast<uint8_t*>(d_states[i]), dp->d, 0u, dp->deg};
+            tasks[i] = vmt::JumpTask{static_cast<uint8_t*>(d_states[i]), dp->d, 0u, dp->deg, nullptr};
         }
     }
     vmt::JumpTask* d_tasks = nullptr;

@@ -41,19 +41,23 @@ inline uint32_t word_bytes(uint32_t variant) { return variant == kMT32 ? 4 : var
 inline uint32_t elems_per_word(uint32_t variant) { return variant == kSFMT ? 4 : 1; }
 
 // One unit of batched work: a state, its output buffer and element count.
+// If `flag` is set (host-visible memory), the workgroup stores 1 there with
+// system-scope release once the task's outputs and state are written.
 struct BatchTask {
     uint8_t* state;
     void* out;
     uint64_t len;
+    uint32_t* flag;
 };
 
 // One jump on one state: lane t uses polynomial slot poly[t] of the table
-// (the same slot for every lane of an ordinary jump).
+// (the same slot for every lane of an ordinary jump). `flag` as for BatchTask.
 struct JumpTask {
     uint8_t* state;
     const uint64_t* poly;  // kPolyWords words; lanes use poly + lane_stride * t
     uint32_t lane_stride;  // 0: one polynomial for all lanes
     uint32_t max_deg;      // highest degree among the lanes' polynomials
+    uint32_t* flag;
 };
 
 }  // namespace vmt

@@ -1,0 +1,22 @@
+// vmt_internal.hpp -- context services shared by the runtime's C++ files.
+#pragma once
+
+#include <cstdint>
+
+#include "vmt.h"
+
+namespace vmt {
+
+// Record an error message for vmt_last_error and return `code`.
+int set_error(int code, const char* fmt, ...);
+
+// Variant and lane count of a registered state (VMT_ESTATE if unknown).
+int ctx_state_info(vmt_ctx* ctx, const void* d_state, int* variant, uint32_t* M);
+
+// Device copy of t^(2^k) mod mu for `variant` (cached by the context) and its degree.
+int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly, uint32_t* degree);
+
+// Device the context runs on (-1 for a host-only context).
+int ctx_device(vmt_ctx* ctx);
+
+}  // namespace vmt

@@ -494,6 +494,12 @@ __global__ __launch_bounds__((mt_threads<P, LANES>()), 8) void batch_mt_kernel(c
         if (t >= count) break;
         const BatchTask task = tasks[t];
         G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, 0, true, win);
+        uint32_t* flag = uniform(task.flag);
+        if (flag) {  // completion signal: every wave's writes first, then one release store
+            __threadfence();
+            __syncthreads();
+            if (wave == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
     if (wave == 0) {
         const uint32_t done = uniform(atomicAdd(counter + 1, lane == 0 ? 1u : 0u));
@@ -889,9 +895,14 @@ __global__ __launch_bounds__(G * 64) void jump_kernel(const JumpTask* tasks, Jum
 __global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t count) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    StateHeader* h = reinterpret_cast<StateHeader*>(tasks ? tasks[i].state : one.state);
+    const JumpTask task = tasks ? tasks[i] : one;
+    StateHeader* h = reinterpret_cast<StateHeader*>(task.state);
     const uint32_t per = h->word_bytes == 16 ? 4u : 1u;
     h->pos = h->pos % (per * h->M);
+    if (task.flag) {
+        __threadfence();
+        __hip_atomic_store(task.flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 }  // namespace

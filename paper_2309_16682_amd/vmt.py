@@ -70,6 +70,9 @@ def lib():
         "vmt_minpoly": ([P, I, P, SZ, IP], I),
         "vmt_jump_poly": ([P, I, P, SZ, P, SZ, IP], I),
         "vmt_set_tuning": ([P, I, U32, U32], I),
+        "vmt_server_create": ([P, P, SZ, P, SZ, U64, I, U32, I, U64, IP], P),
+        "vmt_server_run": ([P, P, SZ, P, I, ctypes.POINTER(ctypes.c_double)], I),
+        "vmt_server_destroy": ([P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -86,6 +89,7 @@ def exported_symbols() -> list:
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
         "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
         "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_set_tuning",
+        "vmt_server_create", "vmt_server_run", "vmt_server_destroy",
     ]
 
 
@@ -262,6 +266,47 @@ def vmt_jump_poly(ctx, variant, distance: int) -> int:
 
 def vmt_set_tuning(ctx, variant, lanes_per_wg, threads=0):
     return _check(lib().vmt_set_tuning(ctx, variant, lanes_per_wg, threads))
+
+
+class vmt_request(ctypes.Structure):
+    _fields_ = [("t_arrival", ctypes.c_double), ("state", ctypes.c_uint32), ("kind", ctypes.c_uint32),
+                ("count", ctypes.c_uint64), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class vmt_result(ctypes.Structure):
+    _fields_ = [("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("out_offset", ctypes.c_uint64), ("status", ctypes.c_int32), ("launch", ctypes.c_int32)]
+
+
+def vmt_server_create(ctx, d_states, d_arena, arena_bytes, budget_bytes, out_kind, n_streams=4, mode=0,
+                      chunk_elems=0):
+    sp = _ptr_array([s if isinstance(s, int) else s.data_ptr() for s in d_states])
+    st = ctypes.c_int(0)
+    h = lib().vmt_server_create(ctx, sp, len(d_states), ctypes.c_void_p(d_arena.data_ptr()), arena_bytes,
+                                budget_bytes, out_kind, n_streams, mode, chunk_elems, ctypes.byref(st))
+    if not h:
+        raise VmtError(st.value, lib().vmt_last_error().decode())
+    return h
+
+
+def vmt_server_run(server, requests, realtime=True):
+    """requests: sequence of (t_arrival, state, kind, count, k). Returns
+    (structured numpy array of results, wall seconds)."""
+    n = len(requests)
+    reqs = (vmt_request * max(n, 1))()
+    for i, (t, st, kind, count, k) in enumerate(requests):
+        reqs[i] = vmt_request(float(t), int(st), int(kind), int(count), int(k), 0)
+    res = (vmt_result * max(n, 1))()
+    wall = ctypes.c_double(0.0)
+    _check(lib().vmt_server_run(server, reqs, n, res, 1 if realtime else 0, ctypes.byref(wall)))
+    dt = np.dtype([("t_admit", "f8"), ("t_launch", "f8"), ("t_done", "f8"), ("out_offset", "u8"), ("status", "i4"),
+                   ("launch", "i4")])
+    out = np.frombuffer(bytes(res), dtype=dt, count=n).copy()
+    return out, wall.value
+
+
+def vmt_server_destroy(server):
+    return _check(lib().vmt_server_destroy(server))
 
 
 # ---- small conveniences (still marshalling only) ---------------------------------

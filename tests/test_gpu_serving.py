@@ -1,0 +1,147 @@
+"""Serving loop on the GPU: every request's result in the mix equals the same
+state's requests replayed alone by the oracle (tolerance 0), the memory budget
+holds, and unservable requests are reported without disturbing the rest."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from tests import golden_io
+from tests.gpu_helpers import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_16682_amd import vmt  # noqa: E402
+from paper_2309_16682_amd.workload import serving_trace  # noqa: E402
+
+MT64 = vmt.VMT_MT64
+M = 8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vmt.vmt_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    vmt.vmt_ctx_destroy(c)
+
+
+def make_states(ctx, n):
+    pool = torch.empty(n * vmt.vmt_state_bytes(MT64, M), dtype=torch.uint8, device="cuda")
+    sb = vmt.vmt_state_bytes(MT64, M)
+    states = [pool[i * sb : (i + 1) * sb] for i in range(n)]
+    for i, st in enumerate(states):
+        vmt.vmt_init_genrand(ctx, MT64, i + 1, M, st)
+    torch.cuda.synchronize()
+    return pool, states
+
+
+def small_trace(n_states, seconds, rate, seed):
+    tr = serving_trace(seconds, rate_per_s=rate, n_states=n_states, min_bytes=8, max_bytes=64 << 10, elem_bytes=8,
+                       jump_fraction=0.15, kmin=32, kmax=80, seed=seed)
+    return [(r.t_arrival, r.state, 0 if r.kind == "gen" else 1, r.nelem if r.kind == "gen" else 0, r.k) for r in tr]
+
+
+def check_against_oracle(reqs, res, arena):
+    mu = golden_io.minpoly(MT64)
+    gJ = golden_io.lane_poly(MT64, M)
+    host = arena.cpu().numpy()
+    by_state = {}
+    for i, r in enumerate(reqs):
+        by_state.setdefault(r[1], []).append(i)
+    for st, idx in by_state.items():
+        ref = O.VStream(MT64, M, O.seed_state(MT64, st + 1), gJ)
+        for i in sorted(idx, key=lambda j: (reqs[j][0], j)):
+            t, _, kind, count, k = reqs[i]
+            assert res[i]["status"] == 0
+            if kind == 1:
+                ref.jump(O.poly_sqr_chain(k, mu))
+            else:
+                off = int(res[i]["out_offset"])
+                got = host[off : off + 8 * count].view(np.uint64)
+                np.testing.assert_array_equal(got, ref.generate(count), err_msg=f"request {i} state {st}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("realtime", [False, True])
+@pytest.mark.parametrize("chunk", [0, 1000])
+def test_results_in_the_mix_equal_each_state_alone(ctx, mode, realtime, chunk):
+    n_states = 24
+    reqs = small_trace(n_states, 0.05, 8000.0, seed=3 + mode)
+    say(f"case serving mode={mode} realtime={realtime} requests={len(reqs)}")
+    total = sum(8 * r[3] for r in reqs) + 256 * len(reqs) + (1 << 20)
+    pool, states = make_states(ctx, n_states)
+    arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    srv = vmt.vmt_server_create(ctx, states, arena, total, total, vmt.VMT_OUT_U64, n_streams=4, mode=mode | 2,
+                                chunk_elems=chunk)
+    try:
+        res, wall = vmt.vmt_server_run(srv, reqs, realtime=realtime)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    assert (res["t_done"] >= res["t_launch"]).all() and (res["t_launch"] >= res["t_admit"]).all()
+    # a state's requests ran one at a time, in arrival order
+    for st in range(n_states):
+        idx = [i for i, r in enumerate(reqs) if r[1] == st]
+        for a, b in zip(idx, idx[1:]):
+            assert res[b]["t_admit"] >= res[a]["t_done"]
+    check_against_oracle(reqs, res, arena)
+
+
+def test_budget_bounds_outputs_in_flight(ctx):
+    n_states = 16
+    reqs = small_trace(n_states, 0.05, 6000.0, seed=9)
+    biggest = max(8 * r[3] for r in reqs)
+    budget = ((biggest + 255) // 256) * 256 * 3  # room for about three outputs at a time
+    say(f"case serving budget={budget} requests={len(reqs)}")
+    pool, states = make_states(ctx, n_states)
+    total = sum(((8 * r[3] + 255) // 256) * 256 for r in reqs) + 256
+    arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    srv = vmt.vmt_server_create(ctx, states, arena, total, budget, vmt.VMT_OUT_U64, n_streams=4, mode=2,
+                                chunk_elems=777)
+    try:
+        res, wall = vmt.vmt_server_run(srv, reqs, realtime=False)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    assert (res["status"] == 0).all()
+    check_against_oracle(reqs, res, arena)
+    ev = []
+    for i, r in enumerate(reqs):
+        if r[2] == 0:
+            b = ((8 * r[3] + 255) // 256) * 256
+            ev.append((res[i]["t_admit"], 1, b))
+            ev.append((res[i]["t_done"], 0, -b))
+    level = 0
+    for t, order, b in sorted(ev):  # releases before admissions at equal times
+        level += b
+        assert level <= budget
+
+
+def test_unservable_requests_are_reported(ctx):
+    pool, states = make_states(ctx, 4)
+    arena = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    reqs = [(0.0, 0, 0, 100, 0), (0.0, 7, 0, 10, 0), (0.0, 1, 0, 1 << 20, 0), (0.0, 2, 1, 0, 1 << 20), (0.0, 3, 0, 5, 0)]
+    srv = vmt.vmt_server_create(ctx, states, arena, 1 << 16, 1 << 16, vmt.VMT_OUT_U64, n_streams=2, mode=0)
+    try:
+        res, wall = vmt.vmt_server_run(srv, reqs, realtime=False)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    assert list(res["status"]) == [0, vmt.VMT_EINVAL, vmt.VMT_EINVAL, vmt.VMT_EINVAL, 0]
+    host = arena.cpu().numpy()
+    gJ = golden_io.lane_poly(MT64, M)
+    for i, st in ((0, 0), (4, 3)):
+        ref = O.VStream(MT64, M, O.seed_state(MT64, st + 1), gJ).generate(reqs[i][3])
+        off = int(res[i]["out_offset"])
+        np.testing.assert_array_equal(host[off : off + 8 * reqs[i][3]].view(np.uint64), ref)
+
+
+def test_server_rejects_mixed_states(ctx):
+    a = vmt.new_state(MT64, 8)
+    b = vmt.new_state(MT64, 4)
+    vmt.vmt_init_genrand(ctx, MT64, 1, 8, a)
+    vmt.vmt_init_genrand(ctx, MT64, 1, 4, b)
+    arena = torch.zeros(1 << 12, dtype=torch.uint8, device="cuda")
+    with pytest.raises(vmt.VmtError) as e:
+        vmt.vmt_server_create(ctx, [a, b], arena, 1 << 12, 1 << 12, vmt.VMT_OUT_U64)
+    assert e.value.code == vmt.VMT_EINVAL
