@@ -12,6 +12,10 @@ slices; the next round overwrites the arena, as a consumer that drains each
 round would). One round = one persistent-kernel launch over its tasks,
 longest first.
 
+The persistent kernel's launch shape is autotuned first on a sample of the
+task lengths; each step is one replay of a HIP graph holding every round's
+launch.
+
 Printed: ONE JSON line with the output GB/s of the step (value), the
 roofline of the persistent kernel (HIP events on its stream), the plain form
 (one launch per generator, same kernel), single-stream rates of the other
@@ -55,6 +59,13 @@ def parse():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-graph", action="store_true", help="launch the rounds eagerly instead of replaying a graph")
+    ap.add_argument("--tune-sample", type=int, default=8192)
+    ap.add_argument("--shape", type=str, default=None,
+                    help="fix the batch shape as threads_variant,store_bytes,wg_per_cu (no autotuning)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only a 4 GiB device copy and fill: the counter scale and the measured write ceiling")
     return ap.parse_args()
 
 
@@ -109,6 +120,27 @@ def cpu_baseline(seconds: float) -> dict:
         f"lengths of the batch workload: {done} uint32 in {dt:.1f} s on one host thread "
         f"({os.cpu_count()} host CPUs)",
     }
+
+
+def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
+    """A plain device copy (read n + write n bytes) and fill (write n bytes)
+    of `gib` GiB: their FETCH_SIZE / WRITE_SIZE readings give the counters'
+    scale, their rate the write ceiling measured on this device."""
+    n = gib << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    out = {"bytes": n}
+    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * n), ("fill", lambda: dst.fill_(7), n)):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name + "_GBps"] = round(moved * reps / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+    return out
 
 
 def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chunk: int = 1 << 20) -> dict:
@@ -191,6 +223,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        print(json.dumps(calibrate(torch)), flush=True)
+        return
     stream = torch.cuda.current_stream()
     ctx = vmt.vmt_ctx_create(0)
 
@@ -215,6 +250,28 @@ def main():
     init_ms = e0.elapsed_time(e1)
     log(f"init: {G} generators in {init_ms:.1f} ms (+{host_poly_s:.2f} s host polynomials)")
 
+    # ---- autotune the persistent kernel's launch shape on a sample of the task lengths
+    tune = None
+    if args.shape:
+        tv, sw, wpc = (int(x) for x in args.shape.split(","))
+        vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_BATCH, vmt.VMT_MT32, M_LANES, vmt.VMT_OUT_U32, threads_variant=tv,
+                          store_bytes=sw, wg_per_cu=wpc)
+    elif not args.no_autotune:
+        sample_lens = np.random.default_rng(17).choice(lens, size=min(args.tune_sample, G), replace=False)
+        t0 = time.perf_counter()
+        best, tried = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_BATCH, vmt.VMT_MT32, M_LANES, vmt.VMT_OUT_U32, sample_lens,
+                                       reps=2)
+        tune = {
+            "sample": f"{len(sample_lens)} task lengths drawn from the workload, "
+            f"{float(sample_lens.sum()) * 4 / 1e9:.1f} GB of output per trial",
+            "seconds": round(time.perf_counter() - t0, 2),
+            "best": {k: (round(v, 1) if k == "gbps" else v) for k, v in best.as_dict().items()},
+            "tried": [[t.threads, t.store_bytes, t.wg_per_cu, round(t.gbps, 1)] for t in tried],
+            "tried_columns": ["threads", "store_bytes", "wg_per_cu", "GB/s"],
+        }
+        log(f"autotune: best {tune['best']} of {len(tried)} shapes in {tune['seconds']} s")
+    shape = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_BATCH, vmt.VMT_MT32, M_LANES, vmt.VMT_OUT_U32)
+
     # ---- arena and rounds
     free, _ = torch.cuda.mem_get_info()
     arena_bytes = int(min(args.arena_gib * 2**30, free - 16 * 2**30))
@@ -233,32 +290,48 @@ def main():
     step_out_bytes = int(lens.sum()) * 4
     log(f"rounds: {len(plans)} over a {arena_bytes / 2**30:.1f} GiB arena; {step_out_bytes / 1e9:.1f} GB per step")
 
-    def step(evs=None):
-        for r, p in enumerate(plans):
-            if evs is not None:
-                evs[r][0].record()
-            vmt.vmt_batch_plan_launch(p)
-            if evs is not None:
-                evs[r][1].record()
+    # one step = every round's persistent launch, captured once into a HIP graph and replayed
+    run_stream = torch.cuda.Stream()
+    graph = None
+    if not args.no_graph:
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(run_stream):
+            with torch.cuda.graph(graph, stream=run_stream):
+                for p in plans:
+                    vmt.vmt_batch_plan_launch(p)
+        torch.cuda.synchronize()
+
+    def step():
+        with torch.cuda.stream(run_stream):
+            if graph is not None:
+                graph.replay()
+            else:
+                for p in plans:
+                    vmt.vmt_batch_plan_launch(p)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs_all = []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in plans]
-        step(evs)
-        evs_all.append(evs)
+    for a, b in evs:
+        a.record(run_stream)
+        step()
+        b.record(run_stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    launch_ms = [[a.elapsed_time(b) for a, b in evs] for evs in evs_all]
-    kern_ms_total = float(np.sum(launch_ms))
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    # events bracket each replay on the stream the kernels run on; a replay is
+    # the rounds' launches back to back, so the mean launch duration is the
+    # event time over the number of launches (gaps between them included)
+    kern_ms_total = float(np.sum(step_ms))
+    launch_ms_mean = kern_ms_total / (args.steps * len(plans))
     alg_total = sum(round_alg_bytes) * args.steps
     achieved = alg_total / (kern_ms_total * 1e-3) / 1e9
     value = step_out_bytes / (ms_per_step * 1e-3) / 1e9
-    log(f"batched: {ms_per_step:.2f} ms/step, {value:.1f} GB/s output; kernel avg {np.mean(launch_ms):.3f} ms/launch")
+    log(f"batched: {ms_per_step:.2f} ms/step, {value:.1f} GB/s output; kernel avg {launch_ms_mean:.3f} ms/launch")
 
     result = {
         "metric": METRIC,
@@ -276,13 +349,16 @@ def main():
         "config": {
             "workload": f"batched V-MT19937-32, M=16 lanes, {G} generators (init_by_array keys from "
             f"splitmix64(42)), log-uniform request lengths in [1e3,1e7) uint32 (splitmix64(43)), "
-            f"persistent kernel, longest first",
+            f"persistent kernel, longest first, one HIP graph per step",
             "generators": G,
             "lanes": M_LANES,
             "elements_per_step": int(lens.sum()),
             "output_bytes_per_step": step_out_bytes,
             "rounds": len(plans),
             "arena_gib": round(arena_bytes / 2**30, 1),
+            "launch": "hipGraph replay" if graph is not None else "eager launches",
+            "shape": {"threads": shape.threads, "store_bytes": shape.store_bytes,
+                      "wg_per_cu": shape.wg_per_cu or "max"},
         },
         "roofline": {
             "bound": "hbm",
@@ -292,11 +368,12 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "kernel": "batch_mt_kernel<MT32, 16 lanes, u32>",
-            "avg_launch_ms": round(float(np.mean(launch_ms)), 4),
+            "avg_launch_ms": round(launch_ms_mean, 4),
             "alg_bytes_per_launch": int(np.mean(round_alg_bytes)),
         },
         "init": {"generators": G, "device_ms": round(init_ms, 2), "lane_jumps": G * (M_LANES - 1),
                  "host_poly_s": round(host_poly_s, 3)},
+        "autotune": tune,
     }
     if args.only_batch:
         print(json.dumps(result), flush=True)
@@ -342,6 +419,11 @@ def main():
             ("sfmt_M64_2^28_u32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "u32"),
             ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
         ):
+            okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
+            lpw = None
+            if not args.no_autotune:
+                b, _ = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [min(n, 1 << 24)], reps=2)
+                lpw = b.lanes_per_wg
             st = vmt.new_state(variant, M)
             vmt.vmt_init_genrand(ctx, variant, seed, M, st)
             esz = 8 if kind in ("u64", "f64") else 4
@@ -357,7 +439,7 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             s = e0.elapsed_time(e1) * 1e-3 / reps
-            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3)}
+            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3), "lanes_per_wg": lpw or min(M, 16)}
             log(f"{name}: {sec[name]}")
             del out
         result["single_stream"] = sec

@@ -221,9 +221,48 @@ int vmt_minpoly(vmt_ctx* ctx, int variant, uint64_t* out, size_t cap, int* degre
 int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dist_words, uint64_t* out,
                   size_t cap, int* degree);
 
-/* Launch-shape override for tests and the autotuner: lanes per workgroup
- * (0 = automatic) for single-state generation. */
-int vmt_set_tuning(vmt_ctx* ctx, int variant, uint32_t lanes_per_wg, uint32_t threads);
+/* ---- launch shapes and the autotuner ------------------------------------------
+ * Family VMT_FAMILY_GENERATE is generation from one state (vmt_generate_*,
+ * vmt_uniform_*): the state's M lanes are split over M / lanes_per_wg
+ * workgroups (lanes_per_wg: a power of two dividing M, at most 16; the LDS
+ * window of a workgroup is [n][lanes_per_wg]). Family VMT_FAMILY_BATCH is the
+ * persistent kernel of vmt_batch_generate, batch plans and the serving loop,
+ * one whole state per workgroup: threads_variant v gives each thread 2^v
+ * times the default share of the twist (0, 1, 2; 1 and 2 only for M = 8 and
+ * 16), store_bytes is the width of each output store (16 or 8), wg_per_cu
+ * the resident workgroups per compute unit (0: as many as fit). The context
+ * keeps one shape per (family, variant, M, out_kind); plans and servers take
+ * the shape in force when they are created. Every shape produces the same
+ * bits; only the speed differs. */
+enum { VMT_FAMILY_GENERATE = 0, VMT_FAMILY_BATCH = 1 };
+
+typedef struct {
+    uint32_t lanes_per_wg;    /* generate family */
+    uint32_t threads_variant; /* batch family */
+    uint32_t store_bytes;     /* batch family */
+    uint32_t wg_per_cu;       /* batch family */
+    uint32_t threads;         /* output: threads per workgroup of the batch shape */
+    uint32_t reserved;
+    double gbps;              /* output: output GB/s measured by vmt_autotune (0 if not measured) */
+} vmt_shape;
+
+/* Shape in force; set stores one (NULL: back to the default). VMT_EINVAL for
+ * a shape that is not compiled in. */
+int vmt_shape_get(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, vmt_shape* shape);
+int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const vmt_shape* shape);
+
+/* Time every available shape of a family on scratch states and outputs that
+ * the call allocates and frees (the caller's states are not touched), store
+ * the fastest in the context and return it in *best. Generate family:
+ * lens[0] elements per trial (count = 1). Batch family: one task per entry of
+ * lens (a sample of the lengths the caller will run). Each shape runs once
+ * untimed and `reps` times timed with HIP events on `stream`; the fastest
+ * repetition counts. tried (optional, tried_cap entries) receives every shape
+ * timed, *n_tried their number. Synchronises `stream`; VMT_ENOMEM if the
+ * scratch outputs do not fit. */
+int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const uint64_t* lens,
+                 size_t count, int reps, vmt_shape* best, vmt_shape* tried, size_t tried_cap, size_t* n_tried,
+                 hipStream_t stream);
 
 #ifdef __cplusplus
 }

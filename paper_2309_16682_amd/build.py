@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libvmt.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["gf2poly.cpp", "vmt_capi.cpp", "vmt_serve.cpp"]
+HOST_SOURCES = ["gf2poly.cpp", "vmt_capi.cpp", "vmt_serve.cpp", "vmt_tune.cpp"]
 HIP_SOURCES = ["vmt_kernels.hip"]
 HIP_FLAGS = [
     "-O3",

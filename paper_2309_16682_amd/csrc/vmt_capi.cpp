@@ -73,7 +73,7 @@ struct vmt_ctx {
     std::map<uint64_t, Words> pow2[3];                 // k -> t^(2^k) mod mu
     std::map<uint32_t, LaneTable> lanes[3];            // M -> lane polynomials on the device
     std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device
-    uint32_t lpw[3] = {0, 0, 0};
+    std::map<uint32_t, vmt_shape> shapes;  // shape_key -> launch shape set by the caller or the autotuner
 };
 
 struct vmt_batch_plan {
@@ -82,7 +82,7 @@ struct vmt_batch_plan {
     uint32_t M;
     int out_kind;
     uint32_t count;
-    uint32_t grid;
+    vmt::BatchShape shape;
     vmt::BatchTask* d_tasks;
     uint32_t* d_counter;
 };
@@ -207,10 +207,19 @@ int lookup(vmt_ctx* ctx, const void* d_state, StateInfo* info) {
     return VMT_OK;
 }
 
-uint32_t pick_lpw(vmt_ctx* ctx, int variant, uint32_t M) {
-    uint32_t l = ctx->lpw[variant];
-    if (l && l <= M && M % l == 0 && l <= 16) return l;
-    return M < 16 ? M : 16;
+uint32_t shape_key(int family, int variant, uint32_t M, int out_kind) {
+    return (uint32_t)family | (uint32_t)variant << 1 | (uint32_t)out_kind << 3 | (uint32_t)log2u(M) << 6;
+}
+
+// Shape in force for (family, variant, M, out_kind): the stored one, else the
+// default (caller holds ctx->mu).
+vmt_shape current_shape(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind) {
+    auto it = ctx->shapes.find(shape_key(family, variant, M, out_kind));
+    if (it != ctx->shapes.end()) return it->second;
+    vmt_shape d{};
+    d.lanes_per_wg = M < 16 ? M : 16;
+    d.store_bytes = 16;
+    return d;
 }
 
 size_t out_elem_bytes(int out_kind) { return out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64 ? 8 : 4; }
@@ -228,7 +237,11 @@ int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, h
     if (!d_out) return fail(VMT_EINVAL, "null output");
     if ((uintptr_t)d_out % out_elem_bytes(out_kind))
         return fail(VMT_EINVAL, "output must be aligned to its element size");
-    const uint32_t lpw = pick_lpw(ctx, info.variant, info.M);
+    uint32_t lpw;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        lpw = current_shape(ctx, VMT_FAMILY_GENERATE, info.variant, info.M, out_kind).lanes_per_wg;
+    }
     if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
         return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
     hipError_t e = vmt::launch_generate(info.variant, info.M, lpw, out_kind, static_cast<uint8_t*>(d_state), d_out,
@@ -355,6 +368,19 @@ int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly
 }
 
 int ctx_device(vmt_ctx* ctx) { return ctx->device; }
+
+void ctx_batch_shape(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, BatchShape* out) {
+    vmt_shape sh;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        sh = current_shape(ctx, VMT_FAMILY_BATCH, variant, M, out_kind);
+    }
+    out->tv = sh.threads_variant;
+    out->sw = sh.store_bytes;
+    const uint32_t fit = batch_max_per_cu(variant, M, out_kind, out->tv, out->sw);
+    const uint32_t per_cu = sh.wg_per_cu && sh.wg_per_cu < fit ? sh.wg_per_cu : fit;
+    out->grid = per_cu * device_cus(ctx->device);
+}
 
 }  // namespace vmt
 
@@ -568,8 +594,9 @@ int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens
     e = hipMemcpyAsync(d_tasks, tasks.data(), bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = vmt::reset_counters(d_counter, stream);
     if (e == hipSuccess) {
-        const uint32_t grid = vmt::batch_grid(info.variant, info.M, out_kind, ctx->device);
-        e = vmt::launch_batch(info.variant, info.M, out_kind, d_tasks, (uint32_t)count, d_counter, grid, stream);
+        vmt::BatchShape shape;
+        vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
+        e = vmt::launch_batch(info.variant, info.M, out_kind, shape, d_tasks, (uint32_t)count, d_counter, stream);
     }
     (void)hipFreeAsync(d_buf, stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
@@ -608,7 +635,7 @@ vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const
     plan->M = info.M;
     plan->out_kind = out_kind;
     plan->count = (uint32_t)count;
-    plan->grid = vmt::batch_grid(info.variant, info.M, out_kind, ctx->device);
+    vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &plan->shape);
     plan->d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
     plan->d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
     if (status) *status = VMT_OK;
@@ -619,8 +646,8 @@ int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream) {
     if (!plan) return fail(VMT_EINVAL, "null plan");
     int st = set_device(plan->ctx);
     if (st) return st;
-    hipError_t e = vmt::launch_batch(plan->variant, plan->M, plan->out_kind, plan->d_tasks, plan->count,
-                                     plan->d_counter, plan->grid, stream);
+    hipError_t e = vmt::launch_batch(plan->variant, plan->M, plan->out_kind, plan->shape, plan->d_tasks, plan->count,
+                                     plan->d_counter, stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return VMT_OK;
 }
@@ -714,14 +741,45 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
     return VMT_OK;
 }
 
-int vmt_set_tuning(vmt_ctx* ctx, int variant, uint32_t lanes_per_wg, uint32_t threads) {
-    if (!ctx) return fail(VMT_EINVAL, "null context");
-    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
-    if (lanes_per_wg && (!valid_M(lanes_per_wg) || lanes_per_wg > 16))
-        return fail(VMT_EINVAL, "lanes per workgroup must be 0 or a power of two <= 16");
-    (void)threads;
+int vmt_shape_get(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, vmt_shape* shape) {
+    if (!ctx || !shape) return fail(VMT_EINVAL, "null argument");
+    if (family != VMT_FAMILY_GENERATE && family != VMT_FAMILY_BATCH) return fail(VMT_EINVAL, "unknown family %d", family);
+    if (!valid_variant(variant) || !valid_M(M) || out_kind < 0 || out_kind > 3)
+        return fail(VMT_EINVAL, "bad variant, M or output kind");
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->lpw[variant] = lanes_per_wg;
+    *shape = current_shape(ctx, family, variant, M, out_kind);
+    if (family == VMT_FAMILY_BATCH) shape->threads = vmt::batch_threads(variant, M, out_kind, shape->threads_variant,
+                                                                         shape->store_bytes);
+    return VMT_OK;
+}
+
+int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const vmt_shape* shape) {
+    if (!ctx) return fail(VMT_EINVAL, "null context");
+    if (family != VMT_FAMILY_GENERATE && family != VMT_FAMILY_BATCH) return fail(VMT_EINVAL, "unknown family %d", family);
+    if (!valid_variant(variant) || !valid_M(M) || out_kind < 0 || out_kind > 3)
+        return fail(VMT_EINVAL, "bad variant, M or output kind");
+    const uint32_t key = shape_key(family, variant, M, out_kind);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!shape) {
+        ctx->shapes.erase(key);
+        return VMT_OK;
+    }
+    vmt_shape sh = current_shape(ctx, family, variant, M, out_kind);
+    if (family == VMT_FAMILY_GENERATE) {
+        if (!vmt::generate_supported(variant, M, shape->lanes_per_wg, out_kind))
+            return fail(VMT_EINVAL, "lanes per workgroup %u not available for variant %d, M=%u, output kind %d",
+                        shape->lanes_per_wg, variant, M, out_kind);
+        sh.lanes_per_wg = shape->lanes_per_wg;
+    } else {
+        if (!vmt::batch_shape_supported(variant, M, out_kind, shape->threads_variant, shape->store_bytes))
+            return fail(VMT_EINVAL, "batch shape (threads variant %u, %u-byte stores) not available for variant %d, "
+                        "M=%u, output kind %d", shape->threads_variant, shape->store_bytes, variant, M, out_kind);
+        sh.threads_variant = shape->threads_variant;
+        sh.store_bytes = shape->store_bytes;
+        sh.wg_per_cu = shape->wg_per_cu;
+    }
+    sh.gbps = shape->gbps;
+    ctx->shapes[key] = sh;
     return VMT_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <cstdint>
 
 #include "vmt.h"
+#include "vmt_launch.hpp"
 
 namespace vmt {
 
@@ -18,5 +19,8 @@ int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly
 
 // Device the context runs on (-1 for a host-only context).
 int ctx_device(vmt_ctx* ctx);
+
+// Batch launch shape in force for (variant, M, out_kind), with its grid.
+void ctx_batch_shape(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, BatchShape* out);
 
 }  // namespace vmt

@@ -238,16 +238,20 @@ __device__ __forceinline__ T gload(const T* p) {
 // ---------------------------------------------------------------------------
 
 // Threads per workgroup for LPW lanes: enough whole wavefronts that each
-// thread owns at most two columns (fewer live registers, no spills).
-template <class P, int LPW>
+// thread owns at most two columns (fewer live registers, no spills). Shape
+// variant TV gives each thread 2^TV times as many columns (fewer, smaller
+// workgroups, so more of them fit on a compute unit).
+template <class P, int LPW, int TV = 0>
 constexpr int mt_threads() {
     constexpr int V = LPW < P::V ? LPW : P::V;
     constexpr int items = P::D * (LPW / V);
-    constexpr int iters = (items + 1023) / 1024;
+    constexpr int iters0 = ((items + 1023) / 1024) << TV;
+    constexpr int iters = iters0 * 64 > items ? (items + 63) / 64 : iters0;
     return 64 * ((items + 64 * iters - 1) / (64 * iters));
 }
 
-template <class P, int LPW, int THREADS, int OUT>
+// SW: bytes per global store of the output (16: dwordx4, 8: dwordx2).
+template <class P, int LPW, int THREADS, int OUT, int SW = 16>
 struct MtGen {
     using W = typename P::W;
     static constexpr int N = P::N, MM = P::MM, D = P::D;
@@ -265,7 +269,7 @@ struct MtGen {
     using VW = Vec<W, V>;
     using Map = OutOf<OUT, W>;
     using OutT = typename Map::T;
-    static constexpr int CH = 16 / sizeof(OutT);  // output elements per 16-byte store
+    static constexpr int CH = SW / sizeof(OutT) > 0 ? SW / sizeof(OutT) : 1;  // output elements per store
     using VO = Vec<OutT, CH>;
 
     static __device__ __forceinline__ VW ld(const W* win, int row, int off) {
@@ -471,10 +475,13 @@ __global__ __launch_bounds__((mt_threads<P, LPW>())) void gen_mt_kernel(uint8_t*
 // tasks are sorted longest first by the host. counter[0] hands out tasks,
 // counter[1] counts finished workgroups; the last one to finish zeroes both,
 // so the next launch (or graph replay) starts from a clean counter.
-template <class P, int LANES, int OUT>
-__global__ __launch_bounds__((mt_threads<P, LANES>()), 8) void batch_mt_kernel(const BatchTask* tasks, uint32_t count,
-                                                                            uint32_t* counter) {
-    using G = MtGen<P, LANES, mt_threads<P, LANES>(), OUT>;
+// TV and SW select the launch shape (threads per workgroup, store width);
+// the autotuner times them. Fewer threads hold more columns per thread, so
+// the register bound is relaxed with the expected waves per SIMD.
+template <class P, int LANES, int OUT, int TV, int SW>
+__global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) void batch_mt_kernel(
+    const BatchTask* tasks, uint32_t count, uint32_t* counter) {
+    using G = MtGen<P, LANES, mt_threads<P, LANES, TV>(), OUT, SW>;
     __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LANES];
     __shared__ uint32_t s_task;
     const uint32_t wave = uniform(threadIdx.x >> 6);
@@ -1015,21 +1022,43 @@ bool batch_supported(uint32_t variant, uint32_t M, int out_kind) {
     return generate_supported(variant, M, M, out_kind);
 }
 
-template <class K>
-static uint32_t grid_for(K kernel, int threads, int device) {
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
-    return (uint32_t)(per_cu * cus);
+// Shape variants are compiled for 8 and 16 lanes (whole generators of the
+// common widths); other widths have the default shape only.
+bool batch_shape_supported(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw) {
+    if (!batch_supported(variant, M, out_kind) || tv > 2 || (sw != 16 && sw != 8)) return false;
+    return (tv == 0 && sw == 16) || M == 8 || M == 16;
 }
 
-#define VMT_BATCH_KERNEL(P, OUTK)                                                                  \
-    VMT_LPW_SWITCH(M, kern = reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK>); \
-                   threads = mt_threads<P, LL>())
+template <class P, int OUTK, int LL>
+static const void* batch_shape_kernel(uint32_t tv, uint32_t sw, int* threads) {
+    if (tv == 0 && sw == 16) {
+        *threads = mt_threads<P, LL, 0>();
+        return reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 0, 16>);
+    }
+    if constexpr (LL >= 8) {
+        if (tv == 0) {
+            *threads = mt_threads<P, LL, 0>();
+            return reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 0, 8>);
+        }
+        if (tv == 1) {
+            *threads = mt_threads<P, LL, 1>();
+            return sw == 16 ? reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 1, 16>)
+                            : reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 1, 8>);
+        }
+        *threads = mt_threads<P, LL, 2>();
+        return sw == 16 ? reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 2, 16>)
+                        : reinterpret_cast<const void*>(batch_mt_kernel<P, LL, OUTK, 2, 8>);
+    }
+    return nullptr;
+}
 
-static const void* batch_kernel_ptr(uint32_t variant, uint32_t M, int out_kind, int* threads_out) {
+#define VMT_BATCH_KERNEL(P, OUTK) VMT_LPW_SWITCH(M, kern = batch_shape_kernel<P, OUTK, LL>(tv, sw, &threads))
+
+static const void* batch_kernel_ptr(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw,
+                                    int* threads_out) {
     const void* kern = nullptr;
     int threads = 0;
+    if (!batch_shape_supported(variant, M, out_kind, tv, sw)) return nullptr;
     if (variant == kMT32) {
         if (out_kind == kOutU32) { VMT_BATCH_KERNEL(MT32P, 0) }
         else { VMT_BATCH_KERNEL(MT32P, 1) }
@@ -1042,10 +1071,23 @@ static const void* batch_kernel_ptr(uint32_t variant, uint32_t M, int out_kind, 
     return kern;
 }
 
-uint32_t batch_grid(uint32_t variant, uint32_t M, int out_kind, int device) {
+uint32_t batch_threads(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw) {
     int threads = 0;
-    const void* kern = batch_kernel_ptr(variant, M, out_kind, &threads);
-    return grid_for(kern, threads, device);
+    return batch_kernel_ptr(variant, M, out_kind, tv, sw, &threads) ? (uint32_t)threads : 0;
+}
+
+uint32_t batch_max_per_cu(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw) {
+    int threads = 0, per_cu = 0;
+    const void* kern = batch_kernel_ptr(variant, M, out_kind, tv, sw, &threads);
+    if (!kern || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess || per_cu < 1)
+        return 1;
+    return (uint32_t)per_cu;
+}
+
+uint32_t device_cus(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+    return (uint32_t)cus;
 }
 
 hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream) {
@@ -1053,12 +1095,13 @@ hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
-                        uint32_t* d_counter, uint32_t grid, hipStream_t stream) {
-    if (grid > count) grid = count;
+hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape, const BatchTask* d_tasks,
+                        uint32_t count, uint32_t* d_counter, hipStream_t stream) {
+    uint32_t grid = shape.grid > count ? count : shape.grid;
     if (grid == 0) return hipSuccess;
     int threads = 0;
-    const void* kern = batch_kernel_ptr(variant, M, out_kind, &threads);
+    const void* kern = batch_kernel_ptr(variant, M, out_kind, shape.tv, shape.sw, &threads);
+    if (!kern) return hipErrorInvalidValue;
     void* args[] = {(void*)&d_tasks, (void*)&count, (void*)&d_counter};
     return hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, stream);
 }

@@ -38,15 +38,27 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
 hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state,
                            void* d_out, uint64_t len, hipStream_t stream);
 
+// Launch shape of the persistent batch kernel: tv selects threads per
+// workgroup (batch_threads), sw the bytes per output store (16 or 8), grid
+// the number of resident workgroups (capped at the task count).
+struct BatchShape {
+    uint32_t tv = 0;
+    uint32_t sw = 16;
+    uint32_t grid = 0;
+};
+
 // Persistent batched generation. d_counter points to two uint32 that must be
 // zero before the first launch (reset_counters); every launch leaves them zero.
 hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream);
-hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchTask* d_tasks, uint32_t count,
-                        uint32_t* d_counter, uint32_t grid, hipStream_t stream);
+hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape, const BatchTask* d_tasks,
+                        uint32_t count, uint32_t* d_counter, hipStream_t stream);
 
-// Whether the combination is compiled in, and the persistent grid size.
+// Whether the combination is compiled in; threads and occupancy of a shape.
 bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind);
 bool batch_supported(uint32_t variant, uint32_t M, int out_kind);
-uint32_t batch_grid(uint32_t variant, uint32_t M, int out_kind, int device);
+bool batch_shape_supported(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw);
+uint32_t batch_threads(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw);
+uint32_t batch_max_per_cu(uint32_t variant, uint32_t M, int out_kind, uint32_t tv, uint32_t sw);
+uint32_t device_cus(int device);
 
 }  // namespace vmt

@@ -104,7 +104,7 @@ struct vmt_server {
     std::vector<uint8_t*> states;
     uint8_t* arena = nullptr;
     uint64_t capacity = 0;
-    uint32_t grid = 0;
+    vmt::BatchShape shape;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     // batching mode: per stream, room for one task per state of each kind
@@ -178,7 +178,7 @@ vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_stat
     s->arena = static_cast<uint8_t*>(d_arena);
     s->capacity = s->retain ? arena_bytes : std::min<uint64_t>(arena_bytes, budget_bytes);
     s->budget = std::min<uint64_t>(arena_bytes, budget_bytes);
-    s->grid = vmt::batch_grid(s->variant, s->M, out_kind, vmt::ctx_device(ctx));
+    vmt::ctx_batch_shape(ctx, s->variant, s->M, out_kind, &s->shape);
     const size_t cap = n_states;
     for (uint32_t i = 0; i < n_streams; i++) {
         hipStream_t st;
@@ -402,8 +402,9 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
                     if (ng && e == hipSuccess) {
                         e = hipMemcpyAsync(d, s->h_gen[si], ng * sizeof(vmt::BatchTask), hipMemcpyHostToDevice, st);
                         if (e == hipSuccess)
-                            e = vmt::launch_batch(s->variant, s->M, s->out_kind, reinterpret_cast<vmt::BatchTask*>(d), ng,
-                                                  reinterpret_cast<uint32_t*>(d + ctr_off), s->grid, st);
+                            e = vmt::launch_batch(s->variant, s->M, s->out_kind, s->shape,
+                                                  reinterpret_cast<vmt::BatchTask*>(d), ng,
+                                                  reinterpret_cast<uint32_t*>(d + ctr_off), st);
                     }
                     if (e == hipSuccess) e = hipEventRecord(s->events[si], st);
                     if (e != hipSuccess) {
@@ -431,7 +432,11 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
                         uint32_t* ctr = reinterpret_cast<uint32_t*>(
                                             base + n * (sizeof(vmt::BatchTask) + sizeof(vmt::JumpTask))) + 2 * (size_t)r;
                         e = hipMemcpyAsync(dt, &h_one[r], sizeof(vmt::BatchTask), hipMemcpyHostToDevice, st);
-                        if (e == hipSuccess) e = vmt::launch_batch(s->variant, s->M, s->out_kind, dt, 1, ctr, 1, st);
+                        if (e == hipSuccess) {
+                            vmt::BatchShape one = s->shape;
+                            one.grid = 1;
+                            e = vmt::launch_batch(s->variant, s->M, s->out_kind, one, dt, 1, ctr, st);
+                        }
                     } else {
                         auto pp = polys[reqs[r].k];
                         h_onej[r] = vmt::JumpTask{s->states[reqs[r].state], pp.first, 0u, pp.second, &flags[r]};

@@ -1,0 +1,180 @@
+// vmt_tune.cpp -- the launch-shape autotuner.
+//
+// Every candidate shape of a kernel family is run on scratch states and
+// outputs (one untimed launch, then `reps` timed ones, fastest counts); the
+// fastest shape is stored in the context through vmt_shape_set. Shapes
+// change the speed only: the kernels write the same bits whatever the shape.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "vmt.h"
+#include "vmt_common.hpp"
+#include "vmt_internal.hpp"
+#include "vmt_launch.hpp"
+
+namespace {
+
+size_t elem_bytes(int out_kind) { return out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64 ? 8 : 4; }
+
+// Scratch device memory released on every exit path.
+struct Scratch {
+    std::vector<void*> ptrs;
+    void* get(size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+    ~Scratch() {
+        (void)hipDeviceSynchronize();
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+// Fastest of `reps` timed runs of `launch` after one untimed run, in ms.
+template <class F>
+int time_best(F launch, int reps, hipStream_t stream, double* best_ms) {
+    Timer t;
+    if (!t.a || !t.b) return vmt::set_error(VMT_EDEVICE, "hipEventCreate failed");
+    hipError_t e = launch();
+    if (e != hipSuccess) return vmt::set_error(VMT_EDEVICE, "autotune launch: %s", hipGetErrorString(e));
+    double best = 1e300;
+    for (int r = 0; r < reps; r++) {
+        e = hipEventRecord(t.a, stream);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(t.b, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t.b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) return vmt::set_error(VMT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+        best = std::min(best, (double)ms);
+    }
+    *best_ms = best;
+    return VMT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const uint64_t* lens, size_t count,
+                 int reps, vmt_shape* best, vmt_shape* tried, size_t tried_cap, size_t* n_tried, hipStream_t stream) {
+    if (!ctx || !lens || count == 0 || reps < 1) return vmt::set_error(VMT_EINVAL, "bad autotune arguments");
+    if (family != VMT_FAMILY_GENERATE && family != VMT_FAMILY_BATCH)
+        return vmt::set_error(VMT_EINVAL, "unknown family %d", family);
+    if (family == VMT_FAMILY_GENERATE && count != 1)
+        return vmt::set_error(VMT_EINVAL, "the generate family takes one length");
+    const int device = vmt::ctx_device(ctx);
+    if (device < 0) return vmt::set_error(VMT_EDEVICE, "host-only context");
+    if (hipSetDevice(device) != hipSuccess) return vmt::set_error(VMT_EDEVICE, "hipSetDevice");
+    const size_t sb = vmt_state_bytes(variant, M);
+    if (sb == 0) return vmt::set_error(VMT_EINVAL, "bad variant or M");
+    if (family == VMT_FAMILY_BATCH ? !vmt::batch_supported(variant, M, out_kind)
+                                   : !vmt::generate_supported(variant, M, M < 16 ? M : 16, out_kind))
+        return vmt::set_error(VMT_EVARIANT, "output kind %d not available for variant %d, M=%u", out_kind, variant, M);
+
+    const size_t eb = elem_bytes(out_kind);
+    std::vector<uint64_t> offs(count);
+    uint64_t total = 0, out_bytes = 0;
+    for (size_t i = 0; i < count; i++) {
+        offs[i] = total;
+        total += (lens[i] * eb + 255) / 256 * 256;
+        out_bytes += lens[i] * eb;
+    }
+    Scratch scratch;
+    uint8_t* states = static_cast<uint8_t*>(scratch.get(sb * count));
+    uint8_t* out = static_cast<uint8_t*>(scratch.get(std::max<uint64_t>(total, 256)));
+    if (!states || !out) return vmt::set_error(VMT_ENOMEM, "autotune scratch (%zu states, %llu output bytes)", count,
+                                               (unsigned long long)total);
+    // one seeded state, copied to every slot (timing does not depend on the values)
+    int st = vmt_init_genrand(ctx, variant, 1, M, states, stream);
+    if (st) return st;
+    for (size_t i = 1; i < count; i++)
+        if (hipMemcpyAsync(states + i * sb, states, sb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return vmt::set_error(VMT_EDEVICE, "autotune state copy");
+    if (hipStreamSynchronize(stream) != hipSuccess) return vmt::set_error(VMT_EDEVICE, "autotune set-up");
+    (void)vmt_state_release(ctx, states);
+
+    std::vector<vmt_shape> cand;
+    std::vector<double> gbps;
+    if (family == VMT_FAMILY_GENERATE) {
+        for (uint32_t lpw = 1; lpw <= M && lpw <= 16; lpw *= 2) {
+            if (!vmt::generate_supported(variant, M, lpw, out_kind)) continue;
+            double ms = 0;
+            st = time_best([&] { return vmt::launch_generate(variant, M, lpw, out_kind, states, out, lens[0], stream); },
+                           reps, stream, &ms);
+            if (st) return st;
+            vmt_shape sh{};
+            sh.lanes_per_wg = lpw;
+            sh.store_bytes = 16;
+            sh.gbps = out_bytes / (ms * 1e-3) / 1e9;
+            cand.push_back(sh);
+        }
+    } else {
+        std::vector<uint32_t> order(count);
+        std::iota(order.begin(), order.end(), 0u);
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lens[a] > lens[b]; });
+        std::vector<vmt::BatchTask> tasks;
+        for (uint32_t i : order) tasks.push_back(vmt::BatchTask{states + i * sb, out + offs[i], lens[i], nullptr});
+        uint8_t* d_buf = static_cast<uint8_t*>(scratch.get(count * sizeof(vmt::BatchTask) + 512));
+        if (!d_buf) return vmt::set_error(VMT_ENOMEM, "autotune task list");
+        auto* d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
+        auto* d_counter = reinterpret_cast<uint32_t*>(d_buf + (count * sizeof(vmt::BatchTask) + 255) / 256 * 256);
+        if (hipMemcpy(d_tasks, tasks.data(), count * sizeof(vmt::BatchTask), hipMemcpyHostToDevice) != hipSuccess ||
+            vmt::reset_counters(d_counter, stream) != hipSuccess)
+            return vmt::set_error(VMT_EDEVICE, "autotune task upload");
+        const uint32_t cus = vmt::device_cus(device);
+        for (uint32_t tv = 0; tv <= 2; tv++)
+            for (uint32_t sw : {16u, 8u}) {
+                if (!vmt::batch_shape_supported(variant, M, out_kind, tv, sw)) continue;
+                const uint32_t fit = vmt::batch_max_per_cu(variant, M, out_kind, tv, sw);
+                for (uint32_t per_cu = 1; per_cu <= fit; per_cu++) {
+                    vmt::BatchShape shape;
+                    shape.tv = tv;
+                    shape.sw = sw;
+                    shape.grid = per_cu * cus;
+                    double ms = 0;
+                    st = time_best([&] { return vmt::launch_batch(variant, M, out_kind, shape, d_tasks, (uint32_t)count,
+                                                                  d_counter, stream); },
+                                   reps, stream, &ms);
+                    if (st) return st;
+                    vmt_shape sh{};
+                    sh.lanes_per_wg = M;
+                    sh.threads_variant = tv;
+                    sh.store_bytes = sw;
+                    sh.wg_per_cu = per_cu;
+                    sh.threads = vmt::batch_threads(variant, M, out_kind, tv, sw);
+                    sh.gbps = out_bytes / (ms * 1e-3) / 1e9;
+                    cand.push_back(sh);
+                }
+            }
+    }
+    if (cand.empty()) return vmt::set_error(VMT_EVARIANT, "no shape available");
+    size_t bi = 0;
+    for (size_t i = 1; i < cand.size(); i++)
+        if (cand[i].gbps > cand[bi].gbps) bi = i;
+    st = vmt_shape_set(ctx, family, variant, M, out_kind, &cand[bi]);
+    if (st) return st;
+    if (best) *best = cand[bi];
+    if (tried)
+        for (size_t i = 0; i < cand.size() && i < tried_cap; i++) tried[i] = cand[i];
+    if (n_tried) *n_tried = cand.size();
+    return VMT_OK;
+}
+
+}  // extern "C"

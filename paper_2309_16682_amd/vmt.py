@@ -69,7 +69,9 @@ def lib():
         "vmt_state_release": ([P, P], I),
         "vmt_minpoly": ([P, I, P, SZ, IP], I),
         "vmt_jump_poly": ([P, I, P, SZ, P, SZ, IP], I),
-        "vmt_set_tuning": ([P, I, U32, U32], I),
+        "vmt_shape_get": ([P, I, I, U32, I, P], I),
+        "vmt_shape_set": ([P, I, I, U32, I, P], I),
+        "vmt_autotune": ([P, I, I, U32, I, P, SZ, I, P, P, SZ, ctypes.POINTER(SZ), P], I),
         "vmt_server_create": ([P, P, SZ, P, SZ, U64, I, U32, I, U64, IP], P),
         "vmt_server_run": ([P, P, SZ, P, I, ctypes.POINTER(ctypes.c_double)], I),
         "vmt_server_destroy": ([P], I),
@@ -88,7 +90,8 @@ def exported_symbols() -> list:
         "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
         "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
-        "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_set_tuning",
+        "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_shape_get",
+        "vmt_shape_set", "vmt_autotune",
         "vmt_server_create", "vmt_server_run", "vmt_server_destroy",
     ]
 
@@ -264,8 +267,40 @@ def vmt_jump_poly(ctx, variant, distance: int) -> int:
     return int.from_bytes(out.tobytes(), "little")
 
 
-def vmt_set_tuning(ctx, variant, lanes_per_wg, threads=0):
-    return _check(lib().vmt_set_tuning(ctx, variant, lanes_per_wg, threads))
+VMT_FAMILY_GENERATE, VMT_FAMILY_BATCH = 0, 1
+
+
+class vmt_shape(ctypes.Structure):
+    _fields_ = [("lanes_per_wg", ctypes.c_uint32), ("threads_variant", ctypes.c_uint32),
+                ("store_bytes", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("gbps", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+def vmt_shape_get(ctx, family, variant, M, out_kind) -> vmt_shape:
+    sh = vmt_shape()
+    _check(lib().vmt_shape_get(ctx, family, variant, M, out_kind, ctypes.byref(sh)))
+    return sh
+
+
+def vmt_shape_set(ctx, family, variant, M, out_kind, shape=None, **fields):
+    """shape: a vmt_shape, or None with keyword fields (none at all: back to the default)."""
+    if shape is None and fields:
+        shape = vmt_shape(**fields)
+    return _check(lib().vmt_shape_set(ctx, family, variant, M, out_kind, ctypes.byref(shape) if shape else None))
+
+
+def vmt_autotune(ctx, family, variant, M, out_kind, lens, reps=3, stream=None):
+    """Returns (best vmt_shape, list of every vmt_shape timed)."""
+    ln = np.ascontiguousarray(np.asarray(lens, dtype=np.uint64))
+    best = vmt_shape()
+    tried = (vmt_shape * 64)()
+    n = ctypes.c_size_t(0)
+    _check(lib().vmt_autotune(ctx, family, variant, M, out_kind, ln.ctypes.data_as(ctypes.c_void_p), ln.size, reps,
+                              ctypes.byref(best), tried, 64, ctypes.byref(n), _stream(stream)))
+    return best, [tried[i] for i in range(min(n.value, 64))]
 
 
 class vmt_request(ctypes.Structure):

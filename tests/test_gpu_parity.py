@@ -246,14 +246,16 @@ def test_batch_generate_matches_individual_streams(ctx, variant, M, kind):
 @pytest.mark.parametrize("variant,M,lpw", [(MT32, 16, 1), (MT32, 16, 4), (MT32, 64, 16), (MT64, 8, 2), (SFMT, 64, 4)])
 def test_split_lanes_over_workgroups(ctx, variant, M, lpw):
     say(f"case split variant={variant} M={M} lpw={lpw}")
-    vmt.vmt_set_tuning(ctx, variant, lpw)
+    native = vmt.VMT_OUT_U64 if variant == MT64 else vmt.VMT_OUT_U32
+    vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, native, lanes_per_wg=lpw)
     try:
+        assert vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, native).lanes_per_wg == lpw
         st = new_init(ctx, variant, M, 8)
         sizes = [5, BLOCK[variant] * M * 2 + 1, 3]
         got = np.concatenate([gen(ctx, st, variant, s) for s in sizes])
         np.testing.assert_array_equal(got, oracle_prefix(variant, M, 8, len(got)))
     finally:
-        vmt.vmt_set_tuning(ctx, variant, 0)
+        vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, native)
 
 
 def test_export_import_resume(ctx):
