@@ -410,6 +410,9 @@ def main():
     rng = np.random.default_rng(5)
     sample = rng.choice(G, size=min(args.plain_sample, G), replace=False)
     out_base = arena
+    # the plain form: one workgroup per generator, one launch each, no splitting
+    vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, vmt.VMT_MT32, M_LANES, vmt.VMT_OUT_U32, lanes_per_wg=M_LANES,
+                      split_log2=255)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
@@ -423,11 +426,12 @@ def main():
         plain_bytes += n * 4
     e1.record()
     torch.cuda.synchronize()
+    vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, vmt.VMT_MT32, M_LANES, vmt.VMT_OUT_U32)
     plain_s = e0.elapsed_time(e1) * 1e-3
     result["plain"] = {
         "value": round(plain_bytes / plain_s / 1e9, 3),
         "unit": "GB/s",
-        "form": "one vmt_generate_u32 launch per generator, same stream",
+        "form": "one vmt_generate_u32 launch per generator (one workgroup, no splitting), same stream",
         "sample": f"{len(sample)} random generators of the batch, {plain_bytes / 1e9:.2f} GB",
         "speedup_batched_vs_plain": round(value / (plain_bytes / plain_s / 1e9), 1),
     }
@@ -447,10 +451,14 @@ def main():
             ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
         ):
             okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
-            lpw = None
+            lpw = split = None
             if not args.no_autotune:
-                b, _ = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [min(n, 1 << 24)], reps=2)
+                b, tried = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [n], reps=2)
                 lpw = b.lanes_per_wg
+                split = b.split_log2
+                log(f"{name} autotune: " + ", ".join(
+                    f"{'lpw=%d' % t.lanes_per_wg if t.split_log2 == 255 else 'split=2^%d' % t.split_log2}: "
+                    f"{t.gbps:.1f}" for t in tried))
             st = vmt.new_state(variant, M)
             vmt.vmt_init_genrand(ctx, variant, seed, M, st)
             esz = 8 if kind in ("u64", "f64") else 4
@@ -466,7 +474,11 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             s = e0.elapsed_time(e1) * 1e-3 / reps
-            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3), "lanes_per_wg": lpw or min(M, 16)}
+            shp = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind)
+            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3),
+                         "lanes_per_wg": shp.lanes_per_wg,
+                         "split": "never" if shp.split_log2 == 255 else (
+                             "auto" if shp.split_log2 == 0 else f"chunks of 2^{shp.split_log2} lane steps")}
             log(f"{name}: {sec[name]}")
             del out
         result["single_stream"] = sec

@@ -233,7 +233,18 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
  * the resident workgroups per compute unit (0: as many as fit). The context
  * keeps one shape per (family, variant, M, out_kind); plans and servers take
  * the shape in force when they are created. Every shape produces the same
- * bits; only the speed differs. */
+ * bits; only the speed differs.
+ *
+ * Splitting (generate family): a long call is cut into chunks of 2^split_log2
+ * lane steps (2^split_log2 * M stream words); chunk c runs from the state
+ * jumped by c * 2^split_log2 steps (Sec. 3.1; a jump of d steps skips d * M
+ * words of the interleaved stream), chunks 0 .. C-2 on copies, the last on
+ * the state itself, all in one batched launch, so the state ends where the
+ * call ends (on a block grid shifted by the jump). split_log2 = 0 lets the
+ * library decide from the call size, 255 never splits, 4..40 fixes the chunk.
+ * MT19937-32/-64 split only for M <= 16. Splitting needs the jump tables of the
+ * chunk offsets (computed on the host once per chunk length) and a scratch
+ * copy of the state per chunk (stream-ordered allocation). */
 enum { VMT_FAMILY_GENERATE = 0, VMT_FAMILY_BATCH = 1 };
 
 typedef struct {
@@ -242,7 +253,7 @@ typedef struct {
     uint32_t store_bytes;     /* batch family */
     uint32_t wg_per_cu;       /* batch family */
     uint32_t threads;         /* output: threads per workgroup of the batch shape */
-    uint32_t reserved;
+    uint32_t split_log2;      /* generate family, see below */
     double gbps;              /* output: output GB/s measured by vmt_autotune (0 if not measured) */
 } vmt_shape;
 

@@ -58,6 +58,15 @@ struct DevPoly {
     uint32_t deg = 0;
 };
 
+// Jump polynomials for splitting one stream into chunks of 2^v lane steps:
+// slot c - 1 holds t^(c 2^v) mod mu.
+struct SplitTable {
+    std::vector<Words> host;
+    std::vector<uint32_t> deg;
+    uint64_t* d = nullptr;
+    size_t cap = 0, uploaded = 0;
+};
+
 struct LaneTable {
     uint64_t* d = nullptr;  // M slots of kPolyWords words
     uint32_t max_deg = 0;
@@ -74,6 +83,8 @@ struct vmt_ctx {
     std::map<uint32_t, LaneTable> lanes[3];            // M -> lane polynomials on the device
     std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device
     std::map<uint32_t, vmt_shape> shapes;  // shape_key -> launch shape set by the caller or the autotuner
+    std::map<uint32_t, SplitTable> split[3];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
+    std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
 };
 
 struct vmt_batch_plan {
@@ -224,6 +235,145 @@ vmt_shape current_shape(vmt_ctx* ctx, int family, int variant, uint32_t M, int o
 
 size_t out_elem_bytes(int out_kind) { return out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64 ? 8 : 4; }
 
+// ---- splitting one stream over many workgroups --------------------------------
+//
+// A call for n elements is cut into C chunks of 2^v lane steps (2^v * M
+// stream words). Chunk c starts from the state jumped by c * 2^v steps: a
+// jump of d steps on every lane skips exactly d * M words of the interleaved
+// stream (Sec. 3, eq. (combseq)), so chunk c is elements [c E, (c + 1) E) of
+// the request. Chunks 0 .. C-2 run on copies of the state; the state itself
+// is jumped to the last chunk and runs it, so it ends where the call ends.
+// All chunks run as one batched launch.
+
+constexpr uint32_t kNeverSplit = 255;
+constexpr uint64_t kMaxChunks = 65535;  // chunks are a grid dimension
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+int ceil_log2(uint64_t x) { return x <= 1 ? 0 : 64 - __builtin_clzll(x - 1); }
+
+// log2 of the chunk length in lane steps, or -1 for a single launch.
+int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t eb, int out_kind) {
+    if (sh.split_log2 == kNeverSplit) return -1;
+    const uint64_t epw = variant == VMT_SFMT ? 4 : 1;  // stream elements per word
+    if (variant != VMT_SFMT && !vmt::batch_supported(variant, M, out_kind)) return -1;
+    const uint64_t steps = ceil_div(n, M * epw);
+    int v;
+    if (sh.split_log2) {
+        v = (int)sh.split_log2;
+    } else {
+        // Automatic. The jumps of a split call take about a millisecond (one lane jump per wavefront, all in
+        // parallel), so split only calls that would take several times that in one launch: MT19937 from
+        // 64 MiB (one launch writes a few tens of GB/s), SFMT19937 from M MiB (its serial chains run at about
+        // 0.1 GB/s per lane). MT chunks: about 2048 lane jumps per call, at least 1 MiB each; SFMT chunks:
+        // 2^13 lane steps (its per-chunk rate is low, so many chunks pay off).
+        if (variant == VMT_SFMT) {
+            if (n * eb < (uint64_t)M << 20) return -1;
+            v = 13;
+        } else {
+            if (n * eb < (64ull << 20)) return -1;
+            const uint64_t cmax = std::max<uint64_t>(2048 / M, 2);
+            v = std::max(ceil_log2(ceil_div(steps, cmax)), ceil_log2(ceil_div(1u << 20, M * epw * eb)));
+        }
+        while (ceil_div(steps, 1ull << v) > 4096) v++;
+    }
+    while (ceil_div(steps, 1ull << v) > kMaxChunks) v++;
+    if (steps <= (1ull << v)) return -1;
+    return v;
+}
+
+// Table of t^(c 2^v) mod mu for c = 1..need on the device (caller holds ctx->mu).
+int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out) {
+    SplitTable& T = ctx->split[variant][(uint32_t)v];
+    if (T.host.size() < need) {
+        vmt::PolyMod& R = ring(ctx, variant);
+        const Words g1 = pow2(ctx, variant, (uint64_t)v);
+        while (T.host.size() < need) {
+            Words g = T.host.empty() ? g1 : R.mul(T.host.back(), g1);
+            const int d = vmt::poly_degree(g);
+            if (d >= vmt::kPolyWords * 64) return fail(VMT_EINVAL, "polynomial too large");
+            T.deg.push_back(d < 0 ? 0u : (uint32_t)d);
+            T.host.push_back(std::move(g));
+        }
+    }
+    if (T.cap < need) {
+        const size_t cap = std::max<size_t>({need, 2 * T.cap, 16});
+        uint64_t* d = nullptr;
+        hipError_t e = hipMalloc((void**)&d, cap * vmt::kPolyWords * 8);
+        if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(split table): %s", hipGetErrorString(e));
+        if (T.d) ctx->retired.push_back(T.d);
+        T.d = d;
+        T.cap = cap;
+        T.uploaded = 0;
+    }
+    if (T.uploaded < need) {
+        std::vector<uint64_t> buf((need - T.uploaded) * vmt::kPolyWords, 0);
+        for (size_t c = T.uploaded; c < need; c++)
+            std::copy(T.host[c].begin(), T.host[c].begin() + std::min<size_t>(T.host[c].size(), vmt::kPolyWords),
+                      buf.begin() + (c - T.uploaded) * vmt::kPolyWords);
+        hipError_t e = hipMemcpy(T.d + T.uploaded * vmt::kPolyWords, buf.data(), buf.size() * 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
+        T.uploaded = need;
+    }
+    *out = &T;
+    return VMT_OK;
+}
+
+int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64_t n, uint8_t* d_out, int out_kind,
+                   int v, hipStream_t stream) {
+    const uint32_t M = info.M;
+    const uint64_t epw = info.variant == VMT_SFMT ? 4 : 1;
+    const uint64_t E = (1ull << v) * M * epw;  // elements per chunk
+    const uint64_t C = ceil_div(n, E);
+    const size_t eb = out_elem_bytes(out_kind);
+    const uint64_t* polys = nullptr;
+    std::vector<uint32_t> deg;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        SplitTable* T = nullptr;
+        int st = split_table(ctx, info.variant, v, C - 1, &T);
+        if (st) return st;
+        polys = T->d;
+        deg.assign(T->deg.begin(), T->deg.begin() + (C - 1));
+    }
+    const size_t sb = vmt_state_bytes(info.variant, M);
+    const size_t sbs = (sb + 255) / 256 * 256;
+    const size_t off_bt = (C - 1) * sbs;
+    const size_t off_jt = off_bt + (C * sizeof(vmt::BatchTask) + 255) / 256 * 256;
+    const size_t off_ctr = off_jt + ((C - 1) * sizeof(vmt::JumpTask) + 255) / 256 * 256;
+    const size_t total = off_ctr + 256;
+    uint8_t* buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&buf, total, stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
+    std::vector<uint8_t> host(total - off_bt, 0);
+    auto* bt = reinterpret_cast<vmt::BatchTask*>(host.data());
+    auto* jt = reinterpret_cast<vmt::JumpTask*>(host.data() + (off_jt - off_bt));
+    for (uint64_t c = 0; c < C; c++) {
+        uint8_t* st = c + 1 == C ? d_state : buf + c * sbs;  // copies for chunks 0 .. C-2, the state for the last
+        bt[c] = vmt::BatchTask{st, d_out + c * E * eb, c + 1 < C ? E : n - c * E, nullptr};
+        if (c) jt[c - 1] = vmt::JumpTask{st, polys + (c - 1) * vmt::kPolyWords, 0u, deg[c - 1], nullptr};
+    }
+    auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
+    auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
+    auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
+    e = hipMemcpyAsync(buf + off_bt, host.data(), off_ctr - off_bt, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = vmt::launch_replicate(d_state, buf, (uint32_t)sb, sbs, (uint32_t)(C - 1), stream);
+    if (e == hipSuccess) e = vmt::launch_jump(info.variant, M, d_jt, jt[0], (uint32_t)(C - 1), stream);
+    if (e == hipSuccess) {
+        if (info.variant == VMT_SFMT) {
+            e = vmt::launch_batch_sfmt(M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
+        } else {
+            vmt::BatchShape shape;
+            vmt::ctx_batch_shape(ctx, info.variant, M, out_kind, &shape);
+            e = vmt::reset_counters(d_ctr, stream);
+            if (e == hipSuccess)
+                e = vmt::launch_batch(info.variant, M, out_kind, shape, d_bt, (uint32_t)C, d_ctr, stream);
+        }
+    }
+    (void)hipFreeAsync(buf, stream);
+    if (e != hipSuccess) return hip_fail(e, "split generate");
+    return VMT_OK;
+}
+
 int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, hipStream_t stream) {
     int st = set_device(ctx);
     if (st) return st;
@@ -237,13 +387,18 @@ int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, h
     if (!d_out) return fail(VMT_EINVAL, "null output");
     if ((uintptr_t)d_out % out_elem_bytes(out_kind))
         return fail(VMT_EINVAL, "output must be aligned to its element size");
-    uint32_t lpw;
+    vmt_shape sh;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        lpw = current_shape(ctx, VMT_FAMILY_GENERATE, info.variant, info.M, out_kind).lanes_per_wg;
+        sh = current_shape(ctx, VMT_FAMILY_GENERATE, info.variant, info.M, out_kind);
     }
+    const uint32_t lpw = sh.lanes_per_wg;
     if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
         return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
+    const int v = split_log2(sh, info.variant, info.M, n, out_elem_bytes(out_kind), out_kind);
+    if (v >= 0)
+        return generate_split(ctx, info, static_cast<uint8_t*>(d_state), n, static_cast<uint8_t*>(d_out), out_kind, v,
+                              stream);
     hipError_t e = vmt::launch_generate(info.variant, info.M, lpw, out_kind, static_cast<uint8_t*>(d_state), d_out,
                                         n, stream);
     if (e != hipSuccess) return hip_fail(e, "generate launch");
@@ -422,7 +577,9 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
         for (int v = 0; v < 3; v++) {
             for (auto& kv : ctx->lanes[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
+            for (auto& kv : ctx->split[v]) (void)hipFree(kv.second.d);
         }
+        for (void* p : ctx->retired) (void)hipFree(p);
     }
     delete ctx;
     return VMT_OK;
@@ -769,7 +926,10 @@ int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kin
         if (!vmt::generate_supported(variant, M, shape->lanes_per_wg, out_kind))
             return fail(VMT_EINVAL, "lanes per workgroup %u not available for variant %d, M=%u, output kind %d",
                         shape->lanes_per_wg, variant, M, out_kind);
+        if (shape->split_log2 && shape->split_log2 != kNeverSplit && (shape->split_log2 < 4 || shape->split_log2 > 40))
+            return fail(VMT_EINVAL, "split_log2 must be 0 (automatic), 255 (never) or in [4, 40]");
         sh.lanes_per_wg = shape->lanes_per_wg;
+        sh.split_log2 = shape->split_log2;
     } else {
         if (!vmt::batch_shape_supported(variant, M, out_kind, shape->threads_variant, shape->store_bytes))
             return fail(VMT_EINVAL, "batch shape (threads variant %u, %u-byte stores) not available for variant %d, "

@@ -635,6 +635,25 @@ __global__ __launch_bounds__(64) void gen_sfmt_kernel(uint8_t* state, void* out,
     G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
 }
 
+// Batched SFMT generation: workgroup (g, t) runs lane group g of task t.
+// With several groups per state the positions are fixed afterwards
+// (finalize_batch_pos), since every group reads the header first.
+template <int LPW, int OUT>
+__global__ __launch_bounds__(64) void batch_sfmt_kernel(const BatchTask* tasks) {
+    using G = SfmtGen<LPW, OUT>;
+    __shared__ uint4 win[kSfmtN * LPW];
+    const BatchTask task = tasks[blockIdx.y];
+    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
+}
+
+// Copy a whole state (header and window; `bytes` a multiple of 16) from src
+// to `count` slots spaced `stride` bytes apart.
+__global__ void replicate_state(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(dst + stride * blockIdx.y);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < bytes / 16; i += gridDim.x * blockDim.x) d[i] = s[i];
+}
+
 // Position after a call that emitted `len` elements, for launches with several
 // workgroups per state (none of them may touch the header while others read it).
 __global__ void finalize_gen_pos(uint8_t* state, uint64_t len) {
@@ -647,6 +666,18 @@ __global__ void finalize_gen_pos(uint8_t* state, uint64_t len) {
 }
 
 __global__ void reset_counter(uint32_t* c) { c[threadIdx.x] = 0; }
+
+__global__ void finalize_batch_pos(const BatchTask* tasks, uint32_t count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const BatchTask task = tasks[i];
+    StateHeader* hdr = reinterpret_cast<StateHeader*>(task.state);
+    const uint64_t B = hdr->block, pos = hdr->pos, len = task.len;
+    const uint64_t head = len < B - pos ? len : B - pos;
+    const uint64_t rest = len - head;
+    const uint64_t nblocks = (rest + B - 1) / B;
+    hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * B) : (uint32_t)(pos + head);
+}
 
 // ---------------------------------------------------------------------------
 // Raw-sequence regeneration for the jump: rows of a lane-major buffer,
@@ -1088,6 +1119,29 @@ uint32_t device_cus(int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
     return (uint32_t)cus;
+}
+
+hipError_t launch_batch_sfmt(uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks, uint32_t count,
+                             hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const dim3 grid(M / lpw, count), block(64);
+    if (out_kind == kOutU32) {
+        VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<LL, 0><<<grid, block, 0, stream>>>(d_tasks))
+    } else {
+        VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<LL, 1><<<grid, block, 0, stream>>>(d_tasks))
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || lpw == M) return e;
+    finalize_batch_pos<<<(count + 255) / 256, 256, 0, stream>>>(d_tasks, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride, uint32_t count,
+                            hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t per = (bytes / 16 + 255) / 256;
+    replicate_state<<<dim3(per < 64 ? per : 64, count), 256, 0, stream>>>(src, dst, bytes, stride);
+    return hipGetLastError();
 }
 
 hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream) {

@@ -53,6 +53,15 @@ hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream);
 hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape, const BatchTask* d_tasks,
                         uint32_t count, uint32_t* d_counter, hipStream_t stream);
 
+// Batched SFMT generation (one lane group of lpw lanes per workgroup, tasks
+// of one M); positions are maintained like launch_generate's.
+hipError_t launch_batch_sfmt(uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks, uint32_t count,
+                             hipStream_t stream);
+
+// Copy the state at src (bytes, a multiple of 16) to count slots dst + i*stride.
+hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride, uint32_t count,
+                            hipStream_t stream);
+
 // Whether the combination is compiled in; threads and occupancy of a shape.
 bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind);
 bool batch_supported(uint32_t variant, uint32_t M, int out_kind);

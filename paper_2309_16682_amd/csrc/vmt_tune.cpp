@@ -108,24 +108,58 @@ int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind
         if (hipMemcpyAsync(states + i * sb, states, sb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
             return vmt::set_error(VMT_EDEVICE, "autotune state copy");
     if (hipStreamSynchronize(stream) != hipSuccess) return vmt::set_error(VMT_EDEVICE, "autotune set-up");
-    (void)vmt_state_release(ctx, states);
 
     std::vector<vmt_shape> cand;
-    std::vector<double> gbps;
     if (family == VMT_FAMILY_GENERATE) {
+        // Single launches: lanes per workgroup, timed on at most 2^22 elements (their rate does not depend
+        // on the length). Split calls: every chunk length giving 2 to 4096 chunks, timed on the full length.
+        const uint64_t n = lens[0];
+        const uint64_t epw = variant == VMT_SFMT ? 4 : 1;
+        const uint64_t steps = (n + M * epw - 1) / (M * epw);
+        auto call = [&](uint64_t len) -> hipError_t {
+            int r = out_kind == VMT_OUT_U32   ? vmt_generate_u32(ctx, states, len, (uint32_t*)out, stream)
+                    : out_kind == VMT_OUT_U64 ? vmt_generate_u64(ctx, states, len, (uint64_t*)out, stream)
+                    : out_kind == VMT_OUT_F32 ? vmt_uniform_f32(ctx, states, len, (float*)out, stream)
+                                              : vmt_uniform_f64(ctx, states, len, (double*)out, stream);
+            return r == VMT_OK ? hipSuccess : hipErrorLaunchFailure;
+        };
+        std::vector<vmt_shape> shapes;
         for (uint32_t lpw = 1; lpw <= M && lpw <= 16; lpw *= 2) {
             if (!vmt::generate_supported(variant, M, lpw, out_kind)) continue;
-            double ms = 0;
-            st = time_best([&] { return vmt::launch_generate(variant, M, lpw, out_kind, states, out, lens[0], stream); },
-                           reps, stream, &ms);
-            if (st) return st;
             vmt_shape sh{};
             sh.lanes_per_wg = lpw;
             sh.store_bytes = 16;
-            sh.gbps = out_bytes / (ms * 1e-3) / 1e9;
+            sh.split_log2 = 255;
+            shapes.push_back(sh);
+        }
+        const bool can_split = variant == VMT_SFMT || vmt::batch_supported(variant, M, out_kind);
+        for (uint32_t v = 4; can_split && v <= 40; v++) {
+            const uint64_t chunks = (steps + (1ull << v) - 1) >> v;
+            if (chunks < 2) break;
+            if (chunks > 4096 || (1ull << v) * M * epw * eb < (16u << 10)) continue;
+            vmt_shape sh{};
+            sh.lanes_per_wg = M < 16 ? M : 16;
+            sh.store_bytes = 16;
+            sh.split_log2 = v;
+            shapes.push_back(sh);
+        }
+        for (vmt_shape sh : shapes) {
+            st = vmt_shape_set(ctx, family, variant, M, out_kind, &sh);
+            if (st) break;
+            const uint64_t len = sh.split_log2 == 255 ? std::min<uint64_t>(n, 1ull << 22) : n;
+            double ms = 0;
+            st = time_best([&] { return call(len); }, reps, stream, &ms);
+            if (st) break;
+            sh.gbps = len * eb / (ms * 1e-3) / 1e9;
             cand.push_back(sh);
         }
+        (void)vmt_state_release(ctx, states);
+        if (st) {
+            (void)vmt_shape_set(ctx, family, variant, M, out_kind, nullptr);
+            return st;
+        }
     } else {
+        (void)vmt_state_release(ctx, states);
         std::vector<uint32_t> order(count);
         std::iota(order.begin(), order.end(), 0u);
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lens[a] > lens[b]; });

@@ -273,10 +273,10 @@ VMT_FAMILY_GENERATE, VMT_FAMILY_BATCH = 0, 1
 class vmt_shape(ctypes.Structure):
     _fields_ = [("lanes_per_wg", ctypes.c_uint32), ("threads_variant", ctypes.c_uint32),
                 ("store_bytes", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("gbps", ctypes.c_double)]
+                ("split_log2", ctypes.c_uint32), ("gbps", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def vmt_shape_get(ctx, family, variant, M, out_kind) -> vmt_shape:

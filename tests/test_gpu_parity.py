@@ -85,10 +85,14 @@ def test_mt32_config1_full_size_and_lane0_is_std_mt19937(ctx):
     st = new_init(ctx, MT32, 16, 5489)
     got = gen(ctx, st, MT32, n)
     np.testing.assert_array_equal(got[0::16][:100000], stdpins.std_stream(32, 5489, 100000))
-    ref = oracle_stream(MT32, 16, seed=5489).generate(n)
+    o = oracle_stream(MT32, 16, seed=5489)
+    ref = o.generate(n)
     np.testing.assert_array_equal(got, ref)
+    # a long call may be split by jump-ahead, which re-forms the window on a shifted block grid:
+    # the position is within a block and the stream continues exactly
     hdr = vmt.header(vmt.vmt_state_export(ctx, st))
-    assert hdr["pos"] == n - (n // 9984) * 9984  # 4096-element tail of the last block
+    assert 0 <= hdr["pos"] <= 9984
+    np.testing.assert_array_equal(gen(ctx, st, MT32, 20000), o.generate(20000))
 
 
 def test_mt64_config2_full_size_u64_and_f64(ctx):

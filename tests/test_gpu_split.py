@@ -1,0 +1,120 @@
+"""One stream split over many workgroups by jump-ahead: the chunks of a call
+start from copies of the state jumped by c * 2^v lane steps, run in one
+batched launch, and the state ends where the last chunk ends. The output and
+everything generated afterwards must equal the oracle's single stream
+(tolerance 0) for every variant, output kind, chunk length and start position."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from tests.gpu_helpers import as_u, oracle_stream, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_16682_amd import vmt  # noqa: E402
+
+MT32, MT64, SFMT = vmt.VMT_MT32, vmt.VMT_MT64, vmt.VMT_SFMT
+GEN = vmt.VMT_FAMILY_GENERATE
+EPW = {MT32: 1, MT64: 1, SFMT: 4}
+BLOCK = {MT32: 624, MT64: 312, SFMT: 156 * 4}
+DT = {vmt.VMT_OUT_U32: torch.int32, vmt.VMT_OUT_U64: torch.int64, vmt.VMT_OUT_F32: torch.float32,
+      vmt.VMT_OUT_F64: torch.float64}
+CALL = {vmt.VMT_OUT_U32: vmt.vmt_generate_u32, vmt.VMT_OUT_U64: vmt.vmt_generate_u64,
+        vmt.VMT_OUT_F32: vmt.vmt_uniform_f32, vmt.VMT_OUT_F64: vmt.vmt_uniform_f64}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vmt.vmt_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    vmt.vmt_ctx_destroy(c)
+
+
+def native(variant):
+    return vmt.VMT_OUT_U64 if variant == MT64 else vmt.VMT_OUT_U32
+
+
+def run(ctx, st, variant, kind, n):
+    out = torch.zeros(max(n, 1), dtype=DT[kind], device="cuda")
+    CALL[kind](ctx, st, n, out)
+    torch.cuda.synchronize()
+    t = out[:n].cpu()
+    return as_u(t, variant) if kind in (vmt.VMT_OUT_U32, vmt.VMT_OUT_U64) else t.numpy()
+
+
+def expect(variant, kind, raw):
+    if kind in (vmt.VMT_OUT_U32, vmt.VMT_OUT_U64):
+        return raw
+    if kind == vmt.VMT_OUT_F64:
+        return O.map_f64(raw)
+    if variant == MT64:
+        return np.array([O.u64_to_f32(int(u)) for u in raw], np.float32)
+    return O.map_f32(raw)
+
+
+CASES = [
+    # variant, M, kind, split_log2, chunks, start position
+    (MT32, 16, vmt.VMT_OUT_U32, 4, 37.3, 0),
+    (MT32, 16, vmt.VMT_OUT_U32, 12, 3.5, 4321),
+    (MT32, 16, vmt.VMT_OUT_F32, 6, 9.01, 9983),
+    (MT32, 4, vmt.VMT_OUT_U32, 9, 5.5, 17),
+    (MT32, 1, vmt.VMT_OUT_U32, 10, 4.2, 623),
+    (MT64, 8, vmt.VMT_OUT_U64, 5, 20.7, 1),
+    (MT64, 8, vmt.VMT_OUT_F64, 11, 3.1, 2495),
+    (MT64, 16, vmt.VMT_OUT_F32, 7, 6.6, 100),
+    (SFMT, 4, vmt.VMT_OUT_U32, 4, 50.2, 0),
+    (SFMT, 4, vmt.VMT_OUT_F32, 10, 4.5, 2497),
+    (SFMT, 64, vmt.VMT_OUT_U32, 6, 7.7, 333),
+    (SFMT, 1, vmt.VMT_OUT_U32, 12, 3.3, 2),
+]
+
+
+@pytest.mark.parametrize("variant,M,kind,v,chunks,pre", CASES)
+def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre):
+    n = int(chunks * (1 << v) * M * EPW[variant])
+    say(f"case split variant={variant} M={M} kind={kind} v={v} n={n} pre={pre}")
+    seed = 1000 + v
+    st = vmt.new_state(variant, M)
+    vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+    ref = oracle_stream(variant, M, seed=seed)
+    if pre:
+        run(ctx, st, variant, native(variant), pre)  # any start position, single launch
+        ref.generate(pre)
+    vmt.vmt_shape_set(ctx, GEN, variant, M, kind, lanes_per_wg=min(M, 16), split_log2=v)
+    try:
+        got = run(ctx, st, variant, kind, n)
+    finally:
+        vmt.vmt_shape_set(ctx, GEN, variant, M, kind)
+    np.testing.assert_array_equal(got, expect(variant, kind, ref.generate(n)))
+    # the state continues where the split call ended
+    tail = 3 * BLOCK[variant] * M + 5
+    np.testing.assert_array_equal(run(ctx, st, variant, native(variant), tail), ref.generate(tail))
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4), (SFMT, 64)])
+def test_automatic_split_of_a_long_call(ctx, variant, M):
+    # lengths the library splits by itself (several MiB), from a mid-block position
+    n = (6 << 20) // (8 if variant == MT64 else 4) + 12345
+    say(f"case auto split variant={variant} M={M} n={n}")
+    seed = 77
+    st = vmt.new_state(variant, M)
+    vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+    ref = oracle_stream(variant, M, seed=seed)
+    run(ctx, st, variant, native(variant), 999)
+    ref.generate(999)
+    got = run(ctx, st, variant, native(variant), n)
+    np.testing.assert_array_equal(got, ref.generate(n))
+    np.testing.assert_array_equal(run(ctx, st, variant, native(variant), 5000), ref.generate(5000))
+
+
+def test_split_setting_is_validated(ctx):
+    with pytest.raises(vmt.VmtError):
+        vmt.vmt_shape_set(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32, lanes_per_wg=16, split_log2=2)
+    vmt.vmt_shape_set(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32, lanes_per_wg=16, split_log2=255)
+    assert vmt.vmt_shape_get(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32).split_log2 == 255
+    vmt.vmt_shape_set(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32)
+    assert vmt.vmt_shape_get(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32).split_log2 == 0
