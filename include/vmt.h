@@ -168,8 +168,8 @@ int vmt_state_import(vmt_ctx* ctx, void* d_state, const void* h_buf, size_t byte
  * is launched on it as one persistent generation launch (longest first) and
  * one jump launch; launches on different streams overlap. Mode 1 (plain): each
  * admitted request is its own launch, streams taken round robin. Every task
- * raises a completion flag in host memory, so outputs and states are released
- * per request. The output of request i lives at d_arena + results[i].out_offset;
+ * counts into a completion flag in host memory, so outputs and states are
+ * released per request. The output of request i lives at d_arena + results[i].out_offset;
  * by default later requests of the same run reuse the space of completed ones.
  * Mode bit 1 (retain) places outputs one after another instead, so all outputs
  * of a run stay in the arena (the budget still bounds the bytes in flight). */
@@ -193,11 +193,18 @@ typedef struct vmt_server vmt_server;
 
 /* d_states: host array of n_states registered device states; d_arena:
  * 256-byte aligned device memory; out_kind: VMT_OUT_* of the generated
- * elements; 1 <= n_streams <= 16; mode: bit 0 plain launches, bit 1 retain.
- * chunk_elems > 0 serves a generation request in tasks of at most that many
- * elements, one per launch, back to back (the state stays reserved and the
- * output space is held for the whole request), so that no launch is long
- * and newly arrived requests are not queued behind large ones; 0 = one task. */
+ * elements; 1 <= n_streams <= 16 generation streams (mode 0 adds two jump
+ * streams); mode: bit 0 plain launches, bit 1 retain, bit 2 split.
+ * chunk_elems > 0 bounds the elements of one generation task. A larger
+ * request is served either as tasks of at most chunk_elems elements, one per
+ * launch, back to back (the state stays reserved and the output space is held
+ * for the whole request), so that no launch is long and newly arrived
+ * requests are not queued behind large ones; or, with bit 2 (batching mode
+ * only), cut into C chunks of 2^v lane steps (2^v >= chunk_elems / M) that
+ * run side by side: chunk c from the state jumped by c * 2^v steps (Sec. 3.1;
+ * a jump of d steps skips d * M stream words), chunks 0 .. C-2 on copies in
+ * scratch states of the server (2048 of them; a request waits for enough
+ * free ones), the last on the state itself. 0 = one task per request. */
 vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_states, void* d_arena,
                               size_t arena_bytes, uint64_t budget_bytes, int out_kind, uint32_t n_streams,
                               int mode, uint64_t chunk_elems, int* status);

@@ -524,6 +524,17 @@ int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly
 
 int ctx_device(vmt_ctx* ctx) { return ctx->device; }
 
+int ctx_split_polys(vmt_ctx* ctx, int variant, int v, size_t need, const uint64_t** d_table,
+                    std::vector<uint32_t>* degrees) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SplitTable* T = nullptr;
+    int st = split_table(ctx, variant, v, need, &T);
+    if (st) return st;
+    *d_table = T->d;
+    degrees->assign(T->deg.begin(), T->deg.begin() + need);
+    return VMT_OK;
+}
+
 void ctx_batch_shape(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, BatchShape* out) {
     vmt_shape sh;
     {

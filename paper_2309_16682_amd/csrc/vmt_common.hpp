@@ -41,13 +41,20 @@ inline uint32_t word_bytes(uint32_t variant) { return variant == kMT32 ? 4 : var
 inline uint32_t elems_per_word(uint32_t variant) { return variant == kSFMT ? 4 : 1; }
 
 // One unit of batched work: a state, its output buffer and element count.
-// If `flag` is set (host-visible memory), the workgroup stores 1 there with
-// system-scope release once the task's outputs and state are written.
+// If `flag` is set (host-visible memory), the workgroup adds 1 to it with
+// system-scope release once the task's outputs and state are written (several
+// tasks may count into one flag).
 struct BatchTask {
     uint8_t* state;
     void* out;
     uint64_t len;
     uint32_t* flag;
+};
+
+// Copy of a whole state from src to dst.
+struct CopyTask {
+    const uint8_t* src;
+    uint8_t* dst;
 };
 
 // One jump on one state: lane t uses polynomial slot poly[t] of the table

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "vmt.h"
 #include "vmt_launch.hpp"
@@ -22,5 +23,10 @@ int ctx_device(vmt_ctx* ctx);
 
 // Batch launch shape in force for (variant, M, out_kind), with its grid.
 void ctx_batch_shape(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, BatchShape* out);
+
+// Device table of t^(c 2^v) mod mu for c = 1..need (slot c - 1, kPolyWords words each) and the degrees.
+// The table stays valid while the context lives (a larger request may move later calls to a new table).
+int ctx_split_polys(vmt_ctx* ctx, int variant, int v, size_t need, const uint64_t** d_table,
+                    std::vector<uint32_t>* degrees);
 
 }  // namespace vmt

@@ -502,10 +502,12 @@ __global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) vo
         const BatchTask task = tasks[t];
         G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, 0, true, win);
         uint32_t* flag = uniform(task.flag);
-        if (flag) {  // completion signal: every wave's writes first, then one release store
+        if (flag) {  // completion count: every wave's writes first, then one release add (lane 0 adds 1)
             __threadfence();
             __syncthreads();
-            if (wave == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (wave == 0)  // global address space: the compiler folds the wave's adds into one atomic
+                __hip_atomic_fetch_add((VMT_GLOBAL uint32_t*)flag, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     if (wave == 0) {
@@ -644,6 +646,15 @@ __global__ __launch_bounds__(64) void batch_sfmt_kernel(const BatchTask* tasks) 
     __shared__ uint4 win[kSfmtN * LPW];
     const BatchTask task = tasks[blockIdx.y];
     G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
+}
+
+// Copy whole states (header and window; `bytes` a multiple of 16): task y
+// copies tasks[y].src to tasks[y].dst.
+__global__ void copy_states(const CopyTask* tasks, uint32_t bytes) {
+    const CopyTask t = tasks[blockIdx.y];
+    const uint4* s = reinterpret_cast<const uint4*>(t.src);
+    uint4* d = reinterpret_cast<uint4*>(t.dst);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < bytes / 16; i += gridDim.x * blockDim.x) d[i] = s[i];
 }
 
 // Copy a whole state (header and window; `bytes` a multiple of 16) from src
@@ -939,7 +950,7 @@ __global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t 
     h->pos = h->pos % (per * h->M);
     if (task.flag) {
         __threadfence();
-        __hip_atomic_store(task.flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_fetch_add(task.flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1141,6 +1152,13 @@ hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, ui
     if (count == 0) return hipSuccess;
     const uint32_t per = (bytes / 16 + 255) / 256;
     replicate_state<<<dim3(per < 64 ? per : 64, count), 256, 0, stream>>>(src, dst, bytes, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const uint32_t per = (bytes / 16 + 255) / 256;
+    copy_states<<<dim3(per < 64 ? per : 64, count), 256, 0, stream>>>(d_tasks, bytes);
     return hipGetLastError();
 }
 

@@ -58,6 +58,9 @@ hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchS
 hipError_t launch_batch_sfmt(uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks, uint32_t count,
                              hipStream_t stream);
 
+// Copy states: task i copies tasks[i].src to tasks[i].dst (bytes, a multiple of 16).
+hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream);
+
 // Copy the state at src (bytes, a multiple of 16) to count slots dst + i*stride.
 hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride, uint32_t count,
                             hipStream_t stream);

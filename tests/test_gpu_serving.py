@@ -64,13 +64,13 @@ def check_against_oracle(reqs, res, arena):
                 np.testing.assert_array_equal(got, ref.generate(count), err_msg=f"request {i} state {st}")
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode,chunk", [(0, 0), (0, 1000), (1, 0), (1, 1000), (4, 1000), (4, 200)])
 @pytest.mark.parametrize("realtime", [False, True])
-@pytest.mark.parametrize("chunk", [0, 1000])
 def test_results_in_the_mix_equal_each_state_alone(ctx, mode, realtime, chunk):
+    # mode 4: large requests split into chunks that run side by side from jumped copies of the state
     n_states = 24
     reqs = small_trace(n_states, 0.05, 8000.0, seed=3 + mode)
-    say(f"case serving mode={mode} realtime={realtime} requests={len(reqs)}")
+    say(f"case serving mode={mode} chunk={chunk} realtime={realtime} requests={len(reqs)}")
     total = sum(8 * r[3] for r in reqs) + 256 * len(reqs) + (1 << 20)
     pool, states = make_states(ctx, n_states)
     arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
@@ -89,16 +89,17 @@ def test_results_in_the_mix_equal_each_state_alone(ctx, mode, realtime, chunk):
     check_against_oracle(reqs, res, arena)
 
 
-def test_budget_bounds_outputs_in_flight(ctx):
+@pytest.mark.parametrize("mode", [2, 6])
+def test_budget_bounds_outputs_in_flight(ctx, mode):
     n_states = 16
     reqs = small_trace(n_states, 0.05, 6000.0, seed=9)
     biggest = max(8 * r[3] for r in reqs)
     budget = ((biggest + 255) // 256) * 256 * 3  # room for about three outputs at a time
-    say(f"case serving budget={budget} requests={len(reqs)}")
+    say(f"case serving budget={budget} mode={mode} requests={len(reqs)}")
     pool, states = make_states(ctx, n_states)
     total = sum(((8 * r[3] + 255) // 256) * 256 for r in reqs) + 256
     arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
-    srv = vmt.vmt_server_create(ctx, states, arena, total, budget, vmt.VMT_OUT_U64, n_streams=4, mode=2,
+    srv = vmt.vmt_server_create(ctx, states, arena, total, budget, vmt.VMT_OUT_U64, n_streams=4, mode=mode,
                                 chunk_elems=777)
     try:
         res, wall = vmt.vmt_server_run(srv, reqs, realtime=False)
@@ -134,6 +135,15 @@ def test_unservable_requests_are_reported(ctx):
         ref = O.VStream(MT64, M, O.seed_state(MT64, st + 1), gJ).generate(reqs[i][3])
         off = int(res[i]["out_offset"])
         np.testing.assert_array_equal(host[off : off + 8 * reqs[i][3]].view(np.uint64), ref)
+
+
+def test_split_mode_arguments_are_checked(ctx):
+    pool, states = make_states(ctx, 2)
+    arena = torch.zeros(1 << 12, dtype=torch.uint8, device="cuda")
+    for mode, chunk in ((5, 100), (4, 0)):  # plain form with splitting; splitting without a chunk size
+        with pytest.raises(vmt.VmtError) as e:
+            vmt.vmt_server_create(ctx, states, arena, 1 << 12, 1 << 12, vmt.VMT_OUT_U64, mode=mode, chunk_elems=chunk)
+        assert e.value.code == vmt.VMT_EINVAL
 
 
 def test_server_rejects_mixed_states(ctx):
