@@ -265,10 +265,10 @@ int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t 
         // parallel), so split only calls that would take several times that in one launch: MT19937 from
         // 64 MiB (one launch writes a few tens of GB/s), SFMT19937 from M MiB (its serial chains run at about
         // 0.1 GB/s per lane). MT chunks: about 2048 lane jumps per call, at least 1 MiB each; SFMT chunks:
-        // 2^13 lane steps (its per-chunk rate is low, so many chunks pay off).
+        // 2^14 lane steps (its per-chunk rate is low, so many chunks pay off).
         if (variant == VMT_SFMT) {
             if (n * eb < (uint64_t)M << 20) return -1;
-            v = 13;
+            v = 14;
         } else {
             if (n * eb < (64ull << 20)) return -1;
             const uint64_t cmax = std::max<uint64_t>(2048 / M, 2);

@@ -151,19 +151,56 @@ __device__ __forceinline__ uint64_t temper(uint64_t y) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// ---- SFMT19937, eq. (sfmt_step); 128-bit words as uint4, .x least significant.
-// w <<< 8 moves bits from sub-word j into j + 1; w >>> 8 from j + 1 into j.
-__device__ __forceinline__ uint4 sfmt_next(const uint4 a, const uint4 b, const uint4 c, const uint4 d) {
-    uint4 r;
-    r.x = a.x ^ (a.x << 8) ^ __builtin_amdgcn_alignbit(c.y, c.x, 8);
-    r.y = a.y ^ __builtin_amdgcn_alignbit(a.y, a.x, 24) ^ __builtin_amdgcn_alignbit(c.z, c.y, 8);
-    r.z = a.z ^ __builtin_amdgcn_alignbit(a.z, a.y, 24) ^ __builtin_amdgcn_alignbit(c.w, c.z, 8);
-    r.w = a.w ^ __builtin_amdgcn_alignbit(a.w, a.z, 24) ^ (c.w >> 8);
-    r.x = xor_and(r.x, b.x >> 11, 0xDFFFFFEFu) ^ (d.x << 18);
-    r.y = xor_and(r.y, b.y >> 11, 0xDDFECB7Fu) ^ (d.y << 18);
-    r.z = xor_and(r.z, b.z >> 11, 0xBFFAFFFFu) ^ (d.z << 18);
-    r.w = xor_and(r.w, b.w >> 11, 0xBFFFFFF6u) ^ (d.w << 18);
-    return r;
+// ---- SFMT19937, eq. (sfmt_step): 128-bit words as four 32-bit sub-words,
+// sub-word 0 least significant; w <<< 8 moves bits from sub-word j into
+// j + 1, w >>> 8 from j + 1 into j. Block regeneration by a quad of threads:
+// thread j of the quad owns sub-word j of every 128-bit word of one lane. The recurrence
+// is serial along the words (each new word reads the two before it), so the
+// quad splits each step four ways instead: the two shifts that cross
+// sub-words take the neighbour's value by a quad permutation (DPP). The
+// neighbour's part of w_{k+N-2} is exchanged two steps ahead, off the
+// dependency chain, and the next step's loads are issued before this step's
+// store.
+__device__ __forceinline__ uint32_t quad_next(uint32_t x) {  // value of quad thread j + 1 (j = 3: own)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xF9, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t quad_prev(uint32_t x) {  // value of quad thread j - 1 (j = 0: own)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x90, 0xF, 0xF, false);
+}
+
+// src, dst: sub-word j of word k at [k * ws + j] (u32 units). src == dst runs
+// in place (word k is read before it is written; w_{k+m} for k + m >= N is a
+// new word written m - ... >= 2 steps earlier by this same thread).
+// emit(k, value) is called for every new sub-word in order.
+template <class Emit>
+__device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* dst, int ws, int j, Emit emit) {
+    constexpr int N = kSfmtN, MM = kSfmtM;
+    // the mask K of eq. (sfmt_params), sub-word j
+    const uint32_t K = j == 0 ? 0xDFFFFFEFu : j == 1 ? 0xDDFECB7Fu : j == 2 ? 0xBFFAFFFFu : 0xBFFFFFF6u;
+    const uint32_t lo_mask = j ? ~0u : 0u;  // sub-word 0 has no lower neighbour
+    const uint32_t hi_mask = j < 3 ? ~0u : 0u;  // sub-word 3 has no upper neighbour
+    uint32_t c = src[(N - 2) * ws + j], d = src[(N - 1) * ws + j];
+    uint32_t cn = quad_next(c), dn = quad_next(d);
+    uint32_t a = src[j], b = src[MM * ws + j];
+#pragma unroll 4
+    for (int k = 0; k < N; ++k) {
+        const uint32_t ak = a, bk = b;
+        if (k + 1 < N) {  // next step's operands (never written by this step)
+            a = src[(k + 1) * ws + j];
+            b = k + 1 + MM < N ? src[(k + 1 + MM) * ws + j] : dst[(k + 1 + MM - N) * ws + j];
+        }
+        const uint32_t ap = quad_prev(ak);
+        uint32_t r = ak ^ (ak << 8) ^ (c >> 8) ^ (d << 18);
+        r = xor_and(r, ap >> 24, lo_mask);
+        r = xor_and(r, cn << 24, hi_mask);
+        r = xor_and(r, bk >> 11, K);
+        dst[k * ws + j] = r;
+        emit(k, r);
+        c = d;
+        cn = dn;
+        d = r;
+        dn = quad_next(r);
+    }
 }
 
 // ---- fixed float maps (exact: the kept bits fit the significand)
@@ -530,20 +567,9 @@ struct SfmtGen {
     static constexpr size_t LDS_BYTES = sizeof(uint4) * N * LPW;
     using OutT = typename OutOf<OUT == 0 ? 0 : 1, uint32_t>::T;
 
-    static __device__ __forceinline__ void out_word(OutT* ob, uint32_t o, uint32_t lim, bool vec_ok, const uint4 w) {
-        OutT r[4];
-        if constexpr (OUT == 0) {
-            r[0] = w.x; r[1] = w.y; r[2] = w.z; r[3] = w.w;
-        } else {
-            r[0] = to_f32(w.x); r[1] = to_f32(w.y); r[2] = to_f32(w.z); r[3] = to_f32(w.w);
-        }
-        if (vec_ok && o + 4 <= lim) {
-            *reinterpret_cast<Vec<OutT, 4>*>(ob + o) = Vec<OutT, 4>{{r[0], r[1], r[2], r[3]}};
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (o + j < lim) ob[o + j] = r[j];
-        }
+    static __device__ __forceinline__ OutT map(uint32_t v) {
+        if constexpr (OUT == 0) return v;
+        else return to_f32(v);
     }
     static __device__ __forceinline__ uint32_t sub(const uint4& w, uint32_t j) {
         return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
@@ -590,31 +616,24 @@ struct SfmtGen {
             }
         }
         __syncthreads();
-        const bool vec_ok = (head % 4) == 0 && ((uintptr_t)out % 16) == 0;
-        if (tid < LPW) {
+        // full blocks: lane group q of the workgroup, quad thread j owns sub-word j
+        const int q = tid >> 2, j = tid & 3;
+        uint32_t* w32 = reinterpret_cast<uint32_t*>(win);
+        if (q < LPW) {
             for (uint64_t b = 0; b < nblocks; ++b) {
                 const uint64_t o0 = head + b * B;
                 OutT* ob = out + o0;
                 const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
-                uint4 c = win[(N - 2) * LPW + tid], d = win[(N - 1) * LPW + tid];
-                uint32_t o = 4u * (lane0 + tid);
-#pragma unroll 2
-                for (int k = 0; k < N - MM; ++k) {  // w_{k+m} still old
-                    const uint4 r = sfmt_next(win[k * LPW + tid], win[(k + MM) * LPW + tid], c, d);
-                    win[k * LPW + tid] = r;
-                    c = d;
-                    d = r;
-                    out_word(ob, o, lim, vec_ok, r);
-                    o += 4u * M;
-                }
-#pragma unroll 2
-                for (int k = N - MM; k < N; ++k) {  // w_{k+m} is new word k + m - N
-                    const uint4 r = sfmt_next(win[k * LPW + tid], win[(k + MM - N) * LPW + tid], c, d);
-                    win[k * LPW + tid] = r;
-                    c = d;
-                    d = r;
-                    out_word(ob, o, lim, vec_ok, r);
-                    o += 4u * M;
+                const uint32_t base = 4u * (lane0 + q) + j;  // output index of word 0's sub-word j
+                if (lim == B) {
+                    sfmt_block_quad(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
+                        ob[base + 4u * M * k] = map(r);
+                    });
+                } else {
+                    sfmt_block_quad(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
+                        const uint32_t o = base + 4u * M * k;
+                        if (o < lim) ob[o] = map(r);
+                    });
                 }
             }
         }
@@ -723,17 +742,10 @@ struct SfmtRaw {
 };
 
 __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int stride, int tid) {
-    if (tid >= rows) return;
-    const uint4* s = src + tid * stride;
-    uint4* d = dst + tid * stride;
-    uint4 c = s[kSfmtN - 2], e = s[kSfmtN - 1];
-    for (int k = 0; k < kSfmtN; ++k) {
-        const uint4 b = k < kSfmtN - kSfmtM ? s[k + kSfmtM] : d[k + kSfmtM - kSfmtN];
-        const uint4 r = sfmt_next(s[k], b, c, e);
-        d[k] = r;
-        c = e;
-        e = r;
-    }
+    const int row = tid >> 2, j = tid & 3;  // one quad of threads per row
+    if (row >= rows) return;
+    sfmt_block_quad(reinterpret_cast<const uint32_t*>(src + row * stride), reinterpret_cast<uint32_t*>(dst + row * stride),
+                    4, j, [](int, uint32_t) {});
 }
 
 __device__ __forceinline__ uint32_t xorw(uint32_t a, uint32_t b) { return a ^ b; }
