@@ -782,6 +782,61 @@ __device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const 
     }
 }
 
+// Grouped form: coefficients are taken four at a time. For a group with
+// pattern p (bits of g at 4u .. 4u+3) the contribution to word j is the XOR
+// of x_{4u+e+j} over the set bits e of p, which is word (4u + e0 + j) of the
+// derived row D[p >> e0] (e0 the lowest set bit): D[q]_m = XOR of x_{m+e}
+// over the set bits e of the odd pattern q. One LDS read per non-zero group
+// instead of one per set coefficient: about 15/32 of the reads for a dense g.
+// rows: the eight derived rows (q = 1, 3, .., 15), `rstride` words apart.
+template <class W, int N>
+__device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const W* rows, int rstride,
+                                                  const uint64_t* poly, int k, int b, int max_deg, int lane) {
+    constexpr int S = (N + 63) / 64;
+    int lo = b * N - k, hi = (b + 1) * N - k;  // coefficient range for this block
+    if (lo < 0) lo = 0;
+    if (hi > max_deg + 1) hi = max_deg + 1;
+    if (lo >= hi) return;
+    for (int wi = lo >> 6; wi <= (hi - 1) >> 6; ++wi) {
+        uint64_t bits = poly[wi];
+        const int base = wi * 64;
+        if (base < lo) bits &= ~0ull << (lo - base);
+        if (base + 64 > hi) bits &= (hi - base >= 64) ? ~0ull : ((1ull << (hi - base)) - 1);
+        while (bits) {
+            const int p = __builtin_ctzll(bits);  // lowest set coefficient: e0 = p mod 4 within its group
+            const int u0 = p & ~3;
+            const int q = (int)((bits >> u0) & 0xF) >> (p - u0);  // odd pattern from e0 up
+            bits &= ~(0xFull << u0);
+            const W* src = rows + (q >> 1) * rstride + (k + base + p - b * N) + lane;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (s < S - 1 || lane + 64 * s < N) acc[s] = xorw(acc[s], src[64 * s]);
+        }
+    }
+}
+
+// Derived rows D[q]_m, q = 3, 5, .., 15, for m in [0, 2N) of every row (the
+// raw row is D[1]); words past the window count as zero (no read of a valid
+// group reaches them: the group's highest set coefficient is in range).
+template <class W, int N>
+__device__ __forceinline__ void derive_rows(W* buf, int rows, int rstride, int row_stride, int tid, int nthr) {
+    for (int it = tid; it < rows * 2 * N; it += nthr) {
+        const int r = it / (2 * N), m = it - r * (2 * N);
+        W* x = buf + r * row_stride;
+        const W z = zero_w<W>();
+        const W x0 = x[m], x1 = m + 1 < 2 * N ? x[m + 1] : z, x2 = m + 2 < 2 * N ? x[m + 2] : z,
+                x3 = m + 3 < 2 * N ? x[m + 3] : z;
+        const W d3 = xorw(x0, x1), d5 = xorw(x0, x2), d7 = xorw(d3, x2);
+        x[1 * rstride + m] = d3;
+        x[2 * rstride + m] = d5;
+        x[3 * rstride + m] = d7;
+        x[4 * rstride + m] = xorw(x0, x3);
+        x[5 * rstride + m] = xorw(d3, x3);
+        x[6 * rstride + m] = xorw(d5, x3);
+        x[7 * rstride + m] = xorw(d7, x3);
+    }
+}
+
 // ---- seeding (the base generators' published init_genrand / init_by_array;
 // the paper starts from a given state and leaves seeding open)
 __device__ void seed_mt32(uint32_t* x, const InitTask& t) {
@@ -857,11 +912,23 @@ __device__ void twist_rows<uint4, 156>(const uint4* s, uint4* d, int rows, int s
 // Buffer: rows of 2N words (lower = block b, upper = block b + 1).
 // ---------------------------------------------------------------------------
 
-template <class W, int N, int G, bool INIT>
+// Words of LDS per raw row: the 2N-word window, and with grouped
+// accumulation its seven derived rows after it. Grouped accumulation reads
+// LDS about half as often but needs eight times the LDS per row: it is used
+// where the raw row is shared (seeding: one row for all lanes of a
+// workgroup) and for jumps of few lanes, where latency matters; many lanes
+// at once run faster per coefficient (more of them fit on a compute unit).
+template <int N, bool GROUPED>
+constexpr int jump_row_words() {
+    return GROUPED ? 8 * 2 * N : 2 * N;
+}
+
+template <class W, int N, int G, bool INIT, bool GROUPED>
 __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* poly, uint32_t lane_stride,
                         int max_deg, int k, const InitTask* init, W* buf) {
     constexpr int S = (N + 63) / 64;
     constexpr int ROWS = INIT ? 1 : G;
+    constexpr int RW = jump_row_words<N, GROUPED>();  // words from one raw row to the next
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // lane of the group handled by this wave
@@ -878,30 +945,41 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
     } else {
         for (int i = tid; i < N * G; i += nthr) {
             const int j = i / G, r = i - (i / G) * G;
-            buf[r * 2 * N + j] = gwin[(size_t)j * M + lane0 + r];
+            buf[r * RW + j] = gwin[(size_t)j * M + lane0 + r];
         }
     }
     __syncthreads();
-    twist_rows<W, N>(buf, buf + N, ROWS, 2 * N, tid, nthr);
+    twist_rows<W, N>(buf, buf + N, ROWS, RW, tid, nthr);
     __syncthreads();
+    if constexpr (GROUPED) {
+        derive_rows<W, N>(buf, ROWS, 2 * N, RW, tid, nthr);
+        __syncthreads();
+    }
 
     W acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
     const uint64_t* mypoly = poly + (size_t)lane_stride * (lane0 + w);
-    const W* myrow = buf + (INIT ? 0 : w * 2 * N);
+    const W* myrow = buf + (INIT ? 0 : w * RW);
     const int last_b = (k + max_deg) / N;
     for (int b = 0; b <= last_b; ++b) {
-        if (w < G) accumulate_block<W, N>(acc, myrow, mypoly, k, b, max_deg, lane);
+        if (w < G) {
+            if constexpr (GROUPED) accumulate_block4<W, N>(acc, myrow, 2 * N, mypoly, k, b, max_deg, lane);
+            else accumulate_block<W, N>(acc, myrow, mypoly, k, b, max_deg, lane);
+        }
         if (b == last_b) break;
         __syncthreads();
         for (int i = tid; i < ROWS * N; i += nthr) {  // upper -> lower
             const int r = i / N, j = i - (i / N) * N;
-            buf[r * 2 * N + j] = buf[r * 2 * N + N + j];
+            buf[r * RW + j] = buf[r * RW + N + j];
         }
         __syncthreads();
-        twist_rows<W, N>(buf, buf + N, ROWS, 2 * N, tid, nthr);
+        twist_rows<W, N>(buf, buf + N, ROWS, RW, tid, nthr);
         __syncthreads();
+        if constexpr (GROUPED) {
+            derive_rows<W, N>(buf, ROWS, 2 * N, RW, tid, nthr);
+            __syncthreads();
+        }
     }
     __syncthreads();
     // stage as [j][lane] and store rows of G contiguous words
@@ -922,12 +1000,12 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
 template <class W, int N, int G>
 __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, InitTask one, uint32_t M,
                                                       const uint64_t* lane_polys, uint32_t max_deg, uint32_t variant) {
-    constexpr int BUF = (2 * N > N * G) ? 2 * N : N * G;
+    constexpr int BUF = (jump_row_words<N, true>() > N * G) ? jump_row_words<N, true>() : N * G;
     __shared__ __attribute__((aligned(16))) W buf[BUF];
     const uint32_t groups = M / G;
     const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
     const InitTask task = tasks ? tasks[ti] : one;
-    dephase<W, N, G, true>(task.state, M, g, lane_polys, kPolyWords, (int)max_deg, N, &task, buf);
+    dephase<W, N, G, true, true>(task.state, M, g, lane_polys, kPolyWords, (int)max_deg, N, &task, buf);
     if (g == 0 && threadIdx.x == 0) {
         StateHeader* h = reinterpret_cast<StateHeader*>(task.state);
         h->magic = kMagic;
@@ -941,16 +1019,17 @@ __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, Ini
     }
 }
 
-template <class W, int N, int G>
+template <class W, int N, int G, bool GROUPED>
 __global__ __launch_bounds__(G * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
-    __shared__ __attribute__((aligned(16))) W buf[2 * N * G];
+    __shared__ __attribute__((aligned(16))) W buf[jump_row_words<N, GROUPED>() * G];
     const uint32_t groups = M / G;
     const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
     const JumpTask task = tasks ? tasks[ti] : one;
     const StateHeader* h = reinterpret_cast<const StateHeader*>(task.state);
     const uint32_t per = sizeof(W) == 16 ? 4u : 1u;
     const int k = (int)(h->pos / (per * M));  // words of every lane already consumed
-    dephase<W, N, G, false>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k, nullptr, buf);
+    dephase<W, N, G, false, GROUPED>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k, nullptr,
+                                     buf);
 }
 
 __global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t count) {
@@ -987,6 +1066,19 @@ static int lanes_per_group(uint32_t variant, uint32_t M) {
         default: { constexpr int GG = 16; __VA_ARGS__; break; } \
     }
 
+#define VMT_G2_SWITCH(G, ...)                                 \
+    switch (G) {                                              \
+        case 1: { constexpr int GG = 1; __VA_ARGS__; break; }  \
+        default: { constexpr int GG = 2; __VA_ARGS__; break; } \
+    }
+#define VMT_G8_SWITCH(G, ...)                                 \
+    switch (G) {                                              \
+        case 1: { constexpr int GG = 1; __VA_ARGS__; break; }  \
+        case 2: { constexpr int GG = 2; __VA_ARGS__; break; }  \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; break; }  \
+        default: { constexpr int GG = 8; __VA_ARGS__; break; } \
+    }
+
 hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, const InitTask& one, uint32_t count,
                        const uint64_t* d_lane_polys, uint32_t max_deg, hipStream_t stream) {
     const int G = lanes_per_group(variant, M);
@@ -1003,18 +1095,30 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
 
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
                        hipStream_t stream) {
-    // 2N*G words per workgroup stay within 40 KB of LDS
+    // Up to 1024 lanes: grouped accumulation, two lanes per workgroup (80 KB of
+    // LDS); more: one coefficient at a time, eight lanes (four for SFMT) per
+    // workgroup in 40 KB, so that many more lanes share each compute unit.
+    const bool grouped = (uint64_t)count * M <= 1024;
     int G = lanes_per_group(variant, M);
-    if (variant == kMT32 && G > 8) G = 8;
-    if (variant == kMT64 && G > 8) G = 8;
-    if (variant == kSFMT && G > 4) G = 4;
+    const int cap = grouped ? 2 : (variant == kSFMT ? 4 : 8);
+    if (G > cap) G = cap;
     const dim3 grid(count * (M / G)), block(G * 64);
-    if (variant == kMT32) {
-        VMT_G_SWITCH(G, jump_kernel<uint32_t, 624, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
-    } else if (variant == kMT64) {
-        VMT_G_SWITCH(G, jump_kernel<uint64_t, 312, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
+    if (grouped) {
+        if (variant == kMT32) {
+            VMT_G2_SWITCH(G, jump_kernel<uint32_t, 624, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        } else if (variant == kMT64) {
+            VMT_G2_SWITCH(G, jump_kernel<uint64_t, 312, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        } else {
+            VMT_G2_SWITCH(G, jump_kernel<uint4, 156, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        }
     } else {
-        VMT_G_SWITCH(G, jump_kernel<uint4, 156, GG><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        if (variant == kMT32) {
+            VMT_G8_SWITCH(G, jump_kernel<uint32_t, 624, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        } else if (variant == kMT64) {
+            VMT_G8_SWITCH(G, jump_kernel<uint64_t, 312, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        } else {
+            VMT_G8_SWITCH(G, jump_kernel<uint4, 156, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -42,3 +42,12 @@ def as_u(arr, variant):
     """torch int tensor (cpu) -> numpy unsigned view."""
     a = arr.numpy()
     return a.view(np.uint32) if variant in (0, 2) else a.view(np.uint64)
+
+
+@functools.lru_cache(maxsize=None)
+def pow2_poly(variant, k):
+    """t^(2^k) mod mu by the oracle's squaring, each k built from k - 1 (cached)."""
+    mu = golden_io.minpoly(variant)
+    if k == 0:
+        return O.poly_mod(2, mu)
+    return O.poly_sqrmod(pow2_poly(variant, k - 1), mu)

@@ -5,7 +5,7 @@ import pytest
 
 from oracle import pyoracle as O
 from tests import golden_io, stdpins
-from tests.gpu_helpers import as_u, oracle_prefix, oracle_stream, out_dtype, say
+from tests.gpu_helpers import pow2_poly, as_u, oracle_prefix, oracle_stream, out_dtype, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -175,7 +175,7 @@ def test_jump_pow2_and_composition(ctx, variant, M):
     ref.generate(101)
     for k in (0, 1, 32, 100, 256):
         vmt.vmt_jump_pow2(ctx, st, k)
-        ref.jump(O.poly_sqr_chain(k, mu))
+        ref.jump(pow2_poly(variant, k))
         np.testing.assert_array_equal(gen(ctx, st, variant, 777), ref.generate(777))
     # d1 then d2 equals d1 + d2
     a = new_init(ctx, variant, M, 5)

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import pyoracle as O
 from tests import golden_io
-from tests.gpu_helpers import say
+from tests.gpu_helpers import pow2_poly, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,6 @@ def small_trace(n_states, seconds, rate, seed):
 
 
 def check_against_oracle(reqs, res, arena):
-    mu = golden_io.minpoly(MT64)
     gJ = golden_io.lane_poly(MT64, M)
     host = arena.cpu().numpy()
     by_state = {}
@@ -57,7 +56,7 @@ def check_against_oracle(reqs, res, arena):
             t, _, kind, count, k = reqs[i]
             assert res[i]["status"] == 0
             if kind == 1:
-                ref.jump(O.poly_sqr_chain(k, mu))
+                ref.jump(pow2_poly(MT64, k))
             else:
                 off = int(res[i]["out_offset"])
                 got = host[off : off + 8 * count].view(np.uint64)
