@@ -767,7 +767,7 @@ __device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const 
     if (hi > max_deg + 1) hi = max_deg + 1;
     if (lo >= hi) return;
     for (int wi = lo >> 6; wi <= (hi - 1) >> 6; ++wi) {
-        uint64_t bits = poly[wi];
+        uint64_t bits = uniform(poly[wi]);  // scalar: the loop over coefficients runs on the scalar unit
         const int base = wi * 64;
         if (base < lo) bits &= ~0ull << (lo - base);
         if (base + 64 > hi) bits &= (hi - base >= 64) ? ~0ull : ((1ull << (hi - base)) - 1);
@@ -797,20 +797,35 @@ __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const
     if (lo < 0) lo = 0;
     if (hi > max_deg + 1) hi = max_deg + 1;
     if (lo >= hi) return;
+    const int off0 = k - b * N + lane;
+    auto next_group = [&](uint64_t& bits, int base) {  // row offset of the lowest non-zero group; clears it
+        const int p = __builtin_ctzll(bits);  // lowest set coefficient: e0 = p mod 4 within its group
+        const int u0 = p & ~3;
+        const int q = (int)((bits >> u0) & 0xF) >> (p - u0);  // odd pattern from e0 up
+        bits &= ~(0xFull << u0);
+        return (q >> 1) * rstride + base + p;
+    };
     for (int wi = lo >> 6; wi <= (hi - 1) >> 6; ++wi) {
-        uint64_t bits = poly[wi];
+        uint64_t bits = uniform(poly[wi]);  // scalar: the loop over coefficients runs on the scalar unit
         const int base = wi * 64;
         if (base < lo) bits &= ~0ull << (lo - base);
         if (base + 64 > hi) bits &= (hi - base >= 64) ? ~0ull : ((1ull << (hi - base)) - 1);
         while (bits) {
-            const int p = __builtin_ctzll(bits);  // lowest set coefficient: e0 = p mod 4 within its group
-            const int u0 = p & ~3;
-            const int q = (int)((bits >> u0) & 0xF) >> (p - u0);  // odd pattern from e0 up
-            bits &= ~(0xFull << u0);
-            const W* src = rows + (q >> 1) * rstride + (k + base + p - b * N) + lane;
+            // two groups per round: the second group's reads are in flight with the first's
+            const W* sa = rows + off0 + next_group(bits, base);
+            W va[S], vb[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (s < S - 1 || lane + 64 * s < N) acc[s] = xorw(acc[s], src[64 * s]);
+            for (int s = 0; s < S; ++s) va[s] = (s < S - 1 || lane + 64 * s < N) ? sa[64 * s] : zero_w<W>();
+            if (bits) {
+                const W* sb = rows + off0 + next_group(bits, base);
+#pragma unroll
+                for (int s = 0; s < S; ++s) vb[s] = (s < S - 1 || lane + 64 * s < N) ? sb[64 * s] : zero_w<W>();
+#pragma unroll
+                for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], xorw(va[s], vb[s]));
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], va[s]);
+            }
         }
     }
 }
