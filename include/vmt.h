@@ -232,7 +232,8 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
  * Family VMT_FAMILY_GENERATE is generation from one state (vmt_generate_*,
  * vmt_uniform_*): the state's M lanes are split over M / lanes_per_wg
  * workgroups (lanes_per_wg: a power of two dividing M, at most 16; the LDS
- * window of a workgroup is [n][lanes_per_wg]). Family VMT_FAMILY_BATCH is the
+ * window of a workgroup is [n][lanes_per_wg]; 0 = chosen per call from its
+ * size). Family VMT_FAMILY_BATCH is the
  * persistent kernel of vmt_batch_generate, batch plans and the serving loop,
  * one whole state per workgroup: threads_variant v gives each thread 2^v
  * times the default share of the twist (0, 1, 2; 1 and 2 only for M = 8 and

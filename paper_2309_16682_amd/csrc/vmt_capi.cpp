@@ -227,10 +227,18 @@ uint32_t shape_key(int family, int variant, uint32_t M, int out_kind) {
 vmt_shape current_shape(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind) {
     auto it = ctx->shapes.find(shape_key(family, variant, M, out_kind));
     if (it != ctx->shapes.end()) return it->second;
-    vmt_shape d{};
-    d.lanes_per_wg = M < 16 ? M : 16;
+    vmt_shape d{};  // lanes_per_wg 0: chosen per call (auto_lpw)
     d.store_bytes = 16;
     return d;
+}
+
+// Lanes per workgroup for one launch when the shape leaves it open: MT19937
+// calls of 256 KiB or more run one lane per workgroup (M workgroups write
+// side by side, about twice the rate of one workgroup for all lanes);
+// smaller calls and SFMT19937 keep whole groups of up to 16 lanes.
+uint32_t auto_lpw(int variant, uint32_t M, uint64_t n, size_t eb) {
+    if (variant != VMT_SFMT && n * eb >= (256u << 10)) return 1;
+    return M < 16 ? M : 16;
 }
 
 size_t out_elem_bytes(int out_kind) { return out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64 ? 8 : 4; }
@@ -261,17 +269,18 @@ int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t 
     if (sh.split_log2) {
         v = (int)sh.split_log2;
     } else {
-        // Automatic. The jumps of a split call take about a millisecond (one lane jump per wavefront, all in
-        // parallel), so split only calls that would take several times that in one launch: MT19937 from
-        // 64 MiB (one launch writes a few tens of GB/s), SFMT19937 from M MiB (its serial chains run at about
-        // 0.1 GB/s per lane). MT chunks: about 2048 lane jumps per call, at least 1 MiB each; SFMT chunks:
-        // 2^14 lane steps (its per-chunk rate is low, so many chunks pay off).
+        // Automatic. The jumps of a split call take about 0.7 ms (one lane jump per wavefront, all in
+        // parallel; up to 1024 lanes in the low-latency grouped form), so split only calls that would take
+        // a few times that in one launch: MT19937 from 32 MiB (one launch writes a few tens of GB/s),
+        // SFMT19937 from M MiB (its serial chains run at about 0.25 GB/s per lane). MT chunks: at most 1024
+        // lane jumps per call, at least 1 MiB each; SFMT chunks: 2^14 lane steps (its per-chunk rate is low,
+        // so many chunks pay off).
         if (variant == VMT_SFMT) {
             if (n * eb < (uint64_t)M << 20) return -1;
             v = 14;
         } else {
-            if (n * eb < (64ull << 20)) return -1;
-            const uint64_t cmax = std::max<uint64_t>(2048 / M, 2);
+            if (n * eb < (32ull << 20)) return -1;
+            const uint64_t cmax = std::max<uint64_t>(1024 / M, 2);
             v = std::max(ceil_log2(ceil_div(steps, cmax)), ceil_log2(ceil_div(1u << 20, M * epw * eb)));
         }
         while (ceil_div(steps, 1ull << v) > 4096) v++;
@@ -392,7 +401,7 @@ int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, h
         std::lock_guard<std::mutex> lk(ctx->mu);
         sh = current_shape(ctx, VMT_FAMILY_GENERATE, info.variant, info.M, out_kind);
     }
-    const uint32_t lpw = sh.lanes_per_wg;
+    const uint32_t lpw = sh.lanes_per_wg ? sh.lanes_per_wg : auto_lpw(info.variant, info.M, n, out_elem_bytes(out_kind));
     if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
         return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
     const int v = split_log2(sh, info.variant, info.M, n, out_elem_bytes(out_kind), out_kind);
@@ -934,7 +943,7 @@ int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kin
     }
     vmt_shape sh = current_shape(ctx, family, variant, M, out_kind);
     if (family == VMT_FAMILY_GENERATE) {
-        if (!vmt::generate_supported(variant, M, shape->lanes_per_wg, out_kind))
+        if (shape->lanes_per_wg && !vmt::generate_supported(variant, M, shape->lanes_per_wg, out_kind))
             return fail(VMT_EINVAL, "lanes per workgroup %u not available for variant %d, M=%u, output kind %d",
                         shape->lanes_per_wg, variant, M, out_kind);
         if (shape->split_log2 && shape->split_log2 != kNeverSplit && (shape->split_log2 < 4 || shape->split_log2 > 40))

@@ -97,8 +97,8 @@ def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre):
 
 @pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4), (SFMT, 64)])
 def test_automatic_split_of_a_long_call(ctx, variant, M):
-    # lengths the library splits by itself (several MiB), from a mid-block position
-    n = (6 << 20) // (8 if variant == MT64 else 4) + 12345
+    # lengths the library splits by itself (40 MiB for MT19937, 6 MiB for SFMT19937), from a mid-block position
+    n = ((40 << 20) if variant != SFMT else (6 << 20)) // (8 if variant == MT64 else 4) + 12345
     say(f"case auto split variant={variant} M={M} n={n}")
     seed = 77
     st = vmt.new_state(variant, M)
@@ -109,6 +109,18 @@ def test_automatic_split_of_a_long_call(ctx, variant, M):
     got = run(ctx, st, variant, native(variant), n)
     np.testing.assert_array_equal(got, ref.generate(n))
     np.testing.assert_array_equal(run(ctx, st, variant, native(variant), 5000), ref.generate(5000))
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8)])
+def test_automatic_lanes_per_workgroup(ctx, variant, M):
+    # unsplit calls of 256 KiB or more run one lane per workgroup when the shape leaves it open
+    assert vmt.vmt_shape_get(ctx, GEN, variant, M, native(variant)).lanes_per_wg == 0
+    seed = 9
+    st = vmt.new_state(variant, M)
+    vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+    ref = oracle_stream(variant, M, seed=seed)
+    for n in (1000, (300 << 10) // (8 if variant == MT64 else 4) + 3, 777):
+        np.testing.assert_array_equal(run(ctx, st, variant, native(variant), n), ref.generate(n))
 
 
 def test_split_setting_is_validated(ctx):
