@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--arena-gib", type=float, default=96.0)
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-threads", type=int, default=16, help="host threads for the oracle baseline (capped by the CPUs)")
     ap.add_argument("--skip-secondary", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -114,33 +115,76 @@ def plan_rounds(lens: np.ndarray, arena_bytes: int, elem_bytes: int):
         R += 1
 
 
-def cpu_baseline(seconds: float) -> dict:
-    """The oracle, as it is, on the host: a few V-MT19937-32 (M = 16) streams
-    keyed like the batch serve the batch's request lengths in order."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds: float, threads: int) -> dict:
+    """The oracle, as it is, on the host's cores: V-MT19937-32 (M = 16) streams
+    keyed like the batch serve the batch's request lengths, request i on
+    thread i mod T (each thread its own streams; the oracle's C calls run
+    without the interpreter lock). Also the oracle's single-thread rate on the
+    batch sample and on the single-stream configurations."""
+    import threading
+
     from oracle import pyoracle as O
     from paper_2309_16682_amd.workload import batch_keys, batch_lengths
     from tests import golden_io
 
-    keys = batch_keys(4, seed=42)
+    keys = batch_keys(4 * threads, seed=42)
     lens = batch_lengths(N_GEN, seed=43)
     gJ = golden_io.lane_poly(0, M_LANES)
-    streams = [O.VStream(0, M_LANES, O.seed_state(0, key=k), gJ) for k in keys]
-    done = 0
-    i = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        streams[i % len(streams)].generate(int(lens[i]))
-        done += int(lens[i])
-        i += 1
-    dt = time.perf_counter() - t0
+
+    def serve(t, T, budget, out, start=None):
+        streams = [O.VStream(0, M_LANES, O.seed_state(0, key=k), gJ) for k in keys[4 * t : 4 * t + 4]]
+        if start is not None:
+            start.wait()  # every thread's streams are seeded: the timed parts run side by side
+        done = reqs = 0
+        i = t
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            streams[reqs % 4].generate(int(lens[i % N_GEN]))
+            done += int(lens[i % N_GEN])
+            reqs += 1
+            i += T
+        out[t] = (done, reqs, time.perf_counter() - t0)
+
+    res = [None] * threads
+    start = threading.Barrier(threads)
+    workers = [threading.Thread(target=serve, args=(t, threads, seconds, res, start)) for t in range(threads)]
+    for w in workers:
+        w.start()
+    for w in workers:
+        w.join()
+    wall = max(r[2] for r in res)  # the timed part (streams are seeded before the barrier)
+    done = sum(r[0] for r in res)
+    reqs = sum(r[1] for r in res)
+    one = [None]
+    serve(0, 1, min(3.0, seconds), one)
+    single = {}
+    for name, variant, M, seed, n, eb in (("mt32_M16_u32", 0, 16, 5489, 1 << 22, 4), ("mt64_M8_u64", 1, 8, 5489, 1 << 21, 8),
+                                          ("sfmt_M4_u32", 2, 4, 1234, 1 << 22, 4), ("sfmt_M64_u32", 2, 64, 1234, 1 << 22, 4)):
+        st = O.VStream(variant, M, O.seed_state(variant, seed=seed), golden_io.lane_poly(variant, M))
+        t1 = time.perf_counter()
+        st.generate(n)
+        single[name] = round(n * eb / (time.perf_counter() - t1) / 1e9, 4)
     return {
-        "value": round(done * 4 / dt / 1e9, 4),
+        "value": round(done * 4 / wall / 1e9, 4),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"oracle V-MT19937-32 (M=16), 4 init_by_array generators serving the first {i} request "
-        f"lengths of the batch workload: {done} uint32 in {dt:.1f} s on one host thread "
-        f"({os.cpu_count()} host CPUs)",
+        "sample": f"oracle V-MT19937-32 (M=16) serving the batch workload's request lengths from 4 init_by_array "
+        f"generators per thread on {threads} threads: {reqs} requests, {done} uint32 in {wall:.1f} s",
+        "host": f"{cpu_model()}, {os.cpu_count()} CPUs visible",
+        "single_thread_GBps": round(one[0][0] * 4 / one[0][2] / 1e9, 4),
+        "single_thread_single_stream_GBps": single,
     }
 
 
@@ -507,7 +551,7 @@ def main():
         }
         log(f"serving: {result['serving']}")
 
-    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, max(1, min(os.cpu_count() or 1, args.cpu_threads)))
     log(f"cpu baseline: {result['cpu_baseline']['value']} GB/s")
     for p in plans:
         vmt.vmt_batch_plan_destroy(p)
