@@ -81,7 +81,9 @@ struct vmt_ctx {
     std::unique_ptr<vmt::PolyMod> ring[3];
     std::map<uint64_t, Words> pow2[3];                 // k -> t^(2^k) mod mu
     std::map<uint32_t, LaneTable> lanes[3];            // M -> lane polynomials on the device
-    std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device
+    std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device (bounded)
+    std::map<uint32_t, DevPoly> pow2_dev[3];            // k -> t^(2^k) on the device (k <= 65536, never evicted:
+                                                         // servers and batches hold these pointers)
     std::map<uint32_t, vmt_shape> shapes;  // shape_key -> launch shape set by the caller or the autotuner
     std::map<uint32_t, SplitTable> split[3];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
     std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
@@ -186,6 +188,20 @@ int lane_table(vmt_ctx* ctx, int variant, uint32_t M, LaneTable** out) {
     return VMT_OK;
 }
 
+// Device copy of t^(2^k) mod mu (k <= 65536), kept for the context's lifetime.
+int pow2_dev(vmt_ctx* ctx, int variant, uint32_t k, DevPoly** out) {
+    auto& cache = ctx->pow2_dev[variant];
+    auto it = cache.find(k);
+    if (it == cache.end()) {
+        DevPoly dp;
+        int st = upload_poly(pow2(ctx, variant, k), &dp);
+        if (st) return st;
+        it = cache.emplace(k, dp).first;
+    }
+    *out = &it->second;
+    return VMT_OK;
+}
+
 // Device copy of t^d mod mu, cached per distance.
 int jump_table(vmt_ctx* ctx, int variant, const std::vector<uint64_t>& dist, const Words* known, DevPoly** out) {
     auto& cache = ctx->jumps[variant];
@@ -194,7 +210,7 @@ int jump_table(vmt_ctx* ctx, int variant, const std::vector<uint64_t>& dist, con
         *out = &it->second;
         return VMT_OK;
     }
-    if (cache.size() >= 4096) {  // bound the cache; entries may be in use by queued kernels
+    if (cache.size() >= 4096) {  // bound the cache (entries are used only by the call that looked them up)
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
         for (auto& kv : cache) (void)hipFree(kv.second.d);
@@ -521,10 +537,8 @@ int ctx_state_info(vmt_ctx* ctx, const void* d_state, int* variant, uint32_t* M)
 
 int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly, uint32_t* degree) {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const Words& g = pow2(ctx, variant, k);
     DevPoly* dp = nullptr;
-    std::vector<uint64_t> key = {~0ull, k};
-    int st = jump_table(ctx, variant, key, &g, &dp);
+    int st = pow2_dev(ctx, variant, k, &dp);
     if (st) return st;
     *d_poly = dp->d;
     *degree = dp->deg;
@@ -597,6 +611,7 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
         for (int v = 0; v < 3; v++) {
             for (auto& kv : ctx->lanes[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
+            for (auto& kv : ctx->pow2_dev[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->split[v]) (void)hipFree(kv.second.d);
         }
         for (void* p : ctx->retired) (void)hipFree(p);
@@ -699,15 +714,18 @@ int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream) {
     int st = set_device(ctx);
     if (st) return st;
     StateInfo info;
-    Words g;
+    DevPoly* dp = nullptr;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         st = lookup(ctx, d_state, &info);
         if (st) return st;
-        g = pow2(ctx, info.variant, k);
+        st = pow2_dev(ctx, info.variant, k, &dp);
+        if (st) return st;
     }
-    std::vector<uint64_t> key = {~0ull, k};  // distinct from any plain distance key
-    return jump_with(ctx, d_state, key, &g, stream);
+    vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
+    hipError_t e = vmt::launch_jump(info.variant, info.M, nullptr, task, 1, stream);
+    if (e != hipSuccess) return hip_fail(e, "jump launch");
+    return VMT_OK;
 }
 
 int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count, hipStream_t stream) {
@@ -723,10 +741,8 @@ int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks,
         std::lock_guard<std::mutex> lk(ctx->mu);
         for (size_t i = 0; i < count; i++) {
             if (ks[i] > 65536) return fail(VMT_EINVAL, "k must be <= 65536");
-            const Words& g = pow2(ctx, info.variant, ks[i]);
             DevPoly* dp = nullptr;
-            std::vector<uint64_t> key = {~0ull, ks[i]};
-            st = jump_table(ctx, info.variant, key, &g, &dp);
+            st = pow2_dev(ctx, info.variant, ks[i], &dp);
             if (st) return st;
             tasks[i] = vmt::JumpTask{static_cast<uint8_t*>(d_states[i]), dp->d, 0u, dp->deg, nullptr};
         }
