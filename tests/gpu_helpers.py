@@ -44,10 +44,12 @@ def as_u(arr, variant):
     return a.view(np.uint32) if variant in (0, 2) else a.view(np.uint64)
 
 
-@functools.lru_cache(maxsize=None)
+_POW2 = {}
+
+
 def pow2_poly(variant, k):
-    """t^(2^k) mod mu by the oracle's squaring, each k built from k - 1 (cached)."""
-    mu = golden_io.minpoly(variant)
-    if k == 0:
-        return O.poly_mod(2, mu)
-    return O.poly_sqrmod(pow2_poly(variant, k - 1), mu)
+    """t^(2^k) mod mu by the oracle's squaring; every k on the way is kept."""
+    chain = _POW2.setdefault(variant, [O.poly_mod(2, golden_io.minpoly(variant))])
+    while len(chain) <= k:
+        chain.append(O.poly_sqrmod(chain[-1], golden_io.minpoly(variant)))
+    return chain[k]

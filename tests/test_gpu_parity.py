@@ -313,3 +313,48 @@ def test_state_window_after_init_is_first_twisted_block(ctx):
         for t in (0, M - 1):
             lane = O.Scalar(variant, ref.lane_canon(t)).raw(O.STATE_WORDS[variant])
             np.testing.assert_array_equal(win[:, t], lane)
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4)])
+def test_jump_pow2_batch_matches_oracle(ctx, variant, M):
+    # each state of a batch jumped by its own 2^k (repeated k, k = 0), from different positions
+    count = 24
+    rng = np.random.default_rng(12)
+    ks = [0, 1, 32, 32, 255, 256] + [int(x) for x in rng.integers(0, 300, count - 6)]
+    pre = [int(x) for x in rng.integers(0, 3 * BLOCK[variant] * M, count)]
+    say(f"case jump_pow2_batch variant={variant} M={M} count={count}")
+    states = [new_init(ctx, variant, M, 900 + i) for i in range(count)]
+    for st, p in zip(states, pre):
+        gen(ctx, st, variant, p)
+    vmt.vmt_jump_pow2_batch(ctx, states, ks)
+    torch.cuda.synchronize()
+    for i in range(count):
+        ref = oracle_stream(variant, M, seed=900 + i)
+        ref.generate(pre[i])
+        ref.jump(pow2_poly(variant, ks[i]))
+        np.testing.assert_array_equal(gen(ctx, states[i], variant, 1000), ref.generate(1000), err_msg=f"state {i}")
+
+
+def test_jump_pow2_batch_with_more_distinct_k_than_the_distance_cache(ctx):
+    # 4100 distinct k in one batch: every task keeps a valid polynomial while the others are looked up
+    count, M = 4100, 2
+    say(f"case jump_pow2_batch {count} distinct k")
+    sb = vmt.vmt_state_bytes(MT64, M)
+    stride = (sb + 255) // 256 * 256  # states are 256-byte aligned
+    pool = torch.zeros(count * stride, dtype=torch.uint8, device="cuda")
+    states = [pool[i * stride : i * stride + sb] for i in range(count)]
+    for i, st in enumerate(states):
+        vmt.vmt_init_genrand(ctx, MT64, 1 + (i % 3), M, st)
+    twins = pool.clone()  # the same states, jumped one call each (that path is checked against the oracle)
+    vmt.vmt_jump_pow2_batch(ctx, states, list(range(count)))
+    torch.cuda.synchronize()
+    for i in range(count):
+        tw = twins[i * stride : i * stride + sb]
+        vmt.vmt_state_import(ctx, tw, tw.cpu().numpy())  # registers the copy with the context
+        vmt.vmt_jump_pow2(ctx, tw, i)
+    torch.cuda.synchronize()
+    assert torch.equal(pool, twins)
+    for i in (0, 1, 2, 300):
+        ref = oracle_stream(MT64, M, seed=1 + (i % 3))
+        ref.jump(pow2_poly(MT64, i))
+        np.testing.assert_array_equal(gen(ctx, states[i], MT64, 700), ref.generate(700), err_msg=f"state {i}")
