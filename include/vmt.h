@@ -136,9 +136,10 @@ int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStr
 
 /* Batched generation: state i writes lens[i] elements of kind out_kind into
  * d_outs[i]. d_states, lens and d_outs are host arrays of count entries; all
- * states must share variant and M. One persistent kernel processes the
- * states longest first from a device work queue. Each state must appear at
- * most once per call. */
+ * states must share variant and M. MT19937-32/-64 (M <= 16): one persistent
+ * kernel processes the states longest first from a device work queue.
+ * SFMT19937: one workgroup per state and group of up to 16 lanes. Each state
+ * must appear at most once per call. */
 int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
                        size_t count, int out_kind, hipStream_t stream);
 

@@ -494,7 +494,10 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
     if (count > 0xFFFFFFFFull) return fail(VMT_EINVAL, "too many tasks");
     int st = check_batch(ctx, d_states, count, info);
     if (st) return st;
-    if (!vmt::batch_supported(info->variant, info->M, out_kind))
+    const bool ok = info->variant == VMT_SFMT
+                        ? vmt::generate_supported(info->variant, info->M, info->M < 16 ? info->M : 16, out_kind)
+                        : vmt::batch_supported(info->variant, info->M, out_kind);
+    if (!ok)
         return fail(VMT_EVARIANT, "batched output kind %d not available for variant %d with M=%u", out_kind,
                     info->variant, info->M);
     {
@@ -509,6 +512,20 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
             return fail(VMT_EINVAL, "output %zu is not aligned to its element size", i);
     }
     return VMT_OK;
+}
+
+// One batched launch: the persistent queue for MT19937; for SFMT19937 one
+// workgroup per task and lane group (its serial chains leave no room for a
+// queue to balance), in slices of at most 65535 tasks (a grid dimension).
+hipError_t launch_tasks(int variant, uint32_t M, int out_kind, const vmt::BatchShape& shape,
+                        const vmt::BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream) {
+    if (variant != VMT_SFMT) return vmt::launch_batch(variant, M, out_kind, shape, d_tasks, count, d_counter, stream);
+    for (uint32_t i = 0; i < count; i += 65535) {
+        hipError_t e = vmt::launch_batch_sfmt(M, M < 16 ? M : 16, out_kind, d_tasks + i, std::min(65535u, count - i),
+                                              stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -788,8 +805,8 @@ int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens
     if (e == hipSuccess) e = vmt::reset_counters(d_counter, stream);
     if (e == hipSuccess) {
         vmt::BatchShape shape;
-        vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
-        e = vmt::launch_batch(info.variant, info.M, out_kind, shape, d_tasks, (uint32_t)count, d_counter, stream);
+        if (info.variant != VMT_SFMT) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
+        e = launch_tasks(info.variant, info.M, out_kind, shape, d_tasks, (uint32_t)count, d_counter, stream);
     }
     (void)hipFreeAsync(d_buf, stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
@@ -828,7 +845,7 @@ vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const
     plan->M = info.M;
     plan->out_kind = out_kind;
     plan->count = (uint32_t)count;
-    vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &plan->shape);
+    if (info.variant != VMT_SFMT) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &plan->shape);
     plan->d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
     plan->d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
     if (status) *status = VMT_OK;
@@ -839,8 +856,8 @@ int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream) {
     if (!plan) return fail(VMT_EINVAL, "null plan");
     int st = set_device(plan->ctx);
     if (st) return st;
-    hipError_t e = vmt::launch_batch(plan->variant, plan->M, plan->out_kind, plan->shape, plan->d_tasks, plan->count,
-                                     plan->d_counter, stream);
+    hipError_t e = launch_tasks(plan->variant, plan->M, plan->out_kind, plan->shape, plan->d_tasks, plan->count,
+                                plan->d_counter, stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return VMT_OK;
 }
