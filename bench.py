@@ -92,29 +92,6 @@ def parse():
     return ap.parse_args()
 
 
-def plan_rounds(lens: np.ndarray, arena_bytes: int, elem_bytes: int):
-    """Deal the tasks (longest first) round-robin over R rounds and give each
-    task a 256-byte aligned slice of the arena within its round."""
-    total = int(sum(((int(n) * elem_bytes + 255) // 256) * 256 for n in lens))
-    R = max(1, -(-total // arena_bytes))
-    while True:
-        order = np.argsort(-lens.astype(np.int64), kind="stable")
-        rounds = [order[r::R] for r in range(R)]
-        offs = {}
-        ok = True
-        for r, idx in enumerate(rounds):
-            off = 0
-            for i in idx:
-                offs[int(i)] = off
-                off += ((int(lens[i]) * elem_bytes + 255) // 256) * 256
-            if off > arena_bytes:
-                ok = False
-                break
-        if ok:
-            return rounds, offs
-        R += 1
-
-
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -287,7 +264,7 @@ def main():
     import torch
 
     from paper_2309_16682_amd import vmt
-    from paper_2309_16682_amd.workload import batch_keys, batch_lengths
+    from paper_2309_16682_amd.workload import batch_keys, batch_lengths, plan_rounds
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")

@@ -9,6 +9,8 @@ request sizes and arrival times.
   serving trace  Poisson arrivals (exponential gaps), log-uniform byte sizes
                  rounded to the element size, uniform state ids, a fraction of
                  jump requests by 2^k with k uniform in [kmin, kmax].
+  rounds         a batch whose outputs exceed the device memory is written in
+                 rounds over an output arena (plan_rounds).
 """
 from __future__ import annotations
 
@@ -86,3 +88,26 @@ def serving_trace(
         Request(i, float(t[i]), int(states[i]), "jump" if is_jump[i] else "gen", int(nelem[i]), int(ks[i]))
         for i in range(n)
     ]
+
+
+def plan_rounds(lens: np.ndarray, arena_bytes: int, elem_bytes: int):
+    """Deal the tasks (longest first) round-robin over R rounds and give each
+    task a 256-byte aligned slice of the arena within its round."""
+    total = int(sum(((int(n) * elem_bytes + 255) // 256) * 256 for n in lens))
+    R = max(1, -(-total // arena_bytes))
+    while True:
+        order = np.argsort(-lens.astype(np.int64), kind="stable")
+        rounds = [order[r::R] for r in range(R)]
+        offs = {}
+        ok = True
+        for r, idx in enumerate(rounds):
+            off = 0
+            for i in idx:
+                offs[int(i)] = off
+                off += ((int(lens[i]) * elem_bytes + 255) // 256) * 256
+            if off > arena_bytes:
+                ok = False
+                break
+        if ok:
+            return rounds, offs
+        R += 1

@@ -1,0 +1,128 @@
+"""The batched and serving workloads at their full sizes, in the launch
+configuration the benchmark times, checked on sampled outputs against the
+oracle (tolerance 0).
+
+  batched: 65,536 V-MT19937-32 (M = 16) generators seeded by init_by_array
+           with splitmix64(42) keys, log-uniform lengths in [1e3, 1e7) from
+           splitmix64(43), the first round of the benchmark's plan (tasks
+           longest first over a 96 GiB arena), autotuned shape, launched from
+           a captured HIP graph; 24 generators compared in full (the longest,
+           the shortest and random ones) and the first 2000 outputs (or all)
+           of 40 more.
+  serving: 4,096 V-MT19937-64 (M = 8) states, the benchmark's trace (Poisson
+           20k/s, 4 KiB - 256 MiB, 10 % jumps by 2^k) for its first 0.25 s,
+           long requests split by jump-ahead, outputs retained; every request
+           completes, and sampled requests equal the oracle replaying their
+           state's history."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import as_u, oracle_stream, pow2_poly, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_16682_amd import vmt  # noqa: E402
+from paper_2309_16682_amd.workload import batch_keys, batch_lengths, plan_rounds, serving_trace  # noqa: E402
+
+MT32, MT64 = vmt.VMT_MT32, vmt.VMT_MT64
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vmt.vmt_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    vmt.vmt_ctx_destroy(c)
+
+
+def test_batched_workload_first_round(ctx):
+    G, M = 65536, 16
+    keys = batch_keys(G, seed=42)
+    lens = batch_lengths(G, seed=43)
+    say("case batched workload: 65536 generators, first round")
+    sb = vmt.vmt_state_bytes(MT32, M)
+    pool = torch.empty(G * sb, dtype=torch.uint8, device="cuda")
+    states = [pool[i * sb : (i + 1) * sb] for i in range(G)]
+    vmt.vmt_init_by_array_batch(ctx, keys, M, states)
+    sample = np.random.default_rng(1).choice(lens, size=4096, replace=False)
+    vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_BATCH, MT32, M, vmt.VMT_OUT_U32, sample, reps=1)
+    arena_bytes = 96 << 30
+    rounds, offs = plan_rounds(lens, arena_bytes, 4)
+    idx = [int(i) for i in rounds[0]]
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    base = arena.data_ptr()
+    plan = vmt.vmt_batch_plan_create(ctx, [states[i].data_ptr() for i in idx], [int(lens[i]) for i in idx],
+                                     [base + offs[i] for i in idx], vmt.VMT_OUT_U32)
+    try:
+        side = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                vmt.vmt_batch_plan_launch(plan)
+        g.replay()
+        torch.cuda.synchronize()
+    finally:
+        vmt.vmt_batch_plan_destroy(plan)
+
+    def out(i, n):
+        return as_u(arena[offs[i] : offs[i] + 4 * n].cpu().view(torch.int32), MT32)
+
+    rng = np.random.default_rng(2)
+    by_len = sorted(idx, key=lambda i: int(lens[i]))
+    full = [by_len[-1], by_len[-2], by_len[0], by_len[1]] + [int(i) for i in rng.choice(idx, 20, replace=False)]
+    for i in full:
+        n = int(lens[i])
+        np.testing.assert_array_equal(out(i, n), oracle_stream(MT32, M, key=keys[i]).generate(n), err_msg=f"gen {i}")
+    for i in rng.choice(idx, 40, replace=False):
+        i = int(i)
+        n = min(2000, int(lens[i]))
+        np.testing.assert_array_equal(out(i, n), oracle_stream(MT32, M, key=keys[i]).generate(n), err_msg=f"gen {i}")
+
+
+def test_serving_workload_sampled(ctx):
+    n_states, M = 4096, 8
+    trace = serving_trace(0.25, rate_per_s=20000.0, n_states=n_states, min_bytes=4096, max_bytes=256 << 20,
+                          elem_bytes=8, jump_fraction=0.1, kmin=32, kmax=256, seed=11)
+    reqs = [(r.t_arrival, r.state, 0 if r.kind == "gen" else 1, r.nelem if r.kind == "gen" else 0, r.k)
+            for r in trace]
+    total = sum(((8 * r[3] + 255) // 256) * 256 for r in reqs) + 256
+    say(f"case serving workload: {len(reqs)} requests, {total / 1e9:.1f} GB retained")
+    sb = vmt.vmt_state_bytes(MT64, M)
+    pool = torch.empty(n_states * sb, dtype=torch.uint8, device="cuda")
+    states = [pool[i * sb : (i + 1) * sb] for i in range(n_states)]
+    for i, st in enumerate(states):
+        vmt.vmt_init_genrand(ctx, MT64, i + 1, M, st)
+    arena = torch.empty(total, dtype=torch.uint8, device="cuda")
+    srv = vmt.vmt_server_create(ctx, states, arena, total, 16 << 30, vmt.VMT_OUT_U64, n_streams=4, mode=4 | 2,
+                                chunk_elems=1 << 20)
+    try:
+        res, wall = vmt.vmt_server_run(srv, reqs, realtime=True)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    assert (res["status"] == 0).all()
+    assert (res["t_done"] >= res["t_admit"]).all()
+    history = {}
+    for i, r in enumerate(reqs):
+        history.setdefault(r[1], []).append(i)
+    gens = [i for i, r in enumerate(reqs) if r[2] == 0]
+    rng = np.random.default_rng(3)
+    largest = max(gens, key=lambda i: reqs[i][3])
+    sample = [largest] + [int(i) for i in rng.choice(gens, 24, replace=False)]
+    for i in sample:
+        st = reqs[i][1]
+        ref = oracle_stream(MT64, M, seed=st + 1)
+        for j in sorted(history[st], key=lambda j: (reqs[j][0], j)):
+            if j == i:
+                break
+            if reqs[j][2] == 1:
+                ref.jump(pow2_poly(MT64, reqs[j][4]))
+            else:
+                ref.generate(reqs[j][3])
+        n = reqs[i][3]
+        off = int(res[i]["out_offset"])
+        got = as_u(arena[off : off + 8 * n].cpu().view(torch.int64), MT64)
+        np.testing.assert_array_equal(got, ref.generate(n), err_msg=f"request {i} state {st} count {n}")
