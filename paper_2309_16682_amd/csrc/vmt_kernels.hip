@@ -61,6 +61,10 @@ __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) 
 __device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) {
     return __builtin_amdgcn_bitop3_b32(a, b, m, (unsigned char)0xE4);
 }
+// a ^ b ^ c in one VALU op (v_bitop3_b32, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, (unsigned char)0x96);
+}
 // all ones if bit 0 of x is set
 __device__ __forceinline__ uint32_t lsb_mask(uint32_t x) { return (uint32_t)__builtin_amdgcn_sbfe((int)x, 0, 1); }
 
@@ -179,8 +183,9 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
     const uint32_t K = j == 0 ? 0xDFFFFFEFu : j == 1 ? 0xDDFECB7Fu : j == 2 ? 0xBFFAFFFFu : 0xBFFFFFF6u;
     const uint32_t lo_mask = j ? ~0u : 0u;  // sub-word 0 has no lower neighbour
     const uint32_t hi_mask = j < 3 ? ~0u : 0u;  // sub-word 3 has no upper neighbour
+    // cn, dn: the upper neighbour's sub-word of c and d, zero for sub-word 3
     uint32_t c = src[(N - 2) * ws + j], d = src[(N - 1) * ws + j];
-    uint32_t cn = quad_next(c), dn = quad_next(d);
+    uint32_t cn = quad_next(c) & hi_mask, dn = quad_next(d) & hi_mask;
     uint32_t a = src[j], b = src[MM * ws + j];
 #pragma unroll 4
     for (int k = 0; k < N; ++k) {
@@ -189,17 +194,18 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
             a = src[(k + 1) * ws + j];
             b = k + 1 + MM < N ? src[(k + 1 + MM) * ws + j] : dst[(k + 1 + MM - N) * ws + j];
         }
-        const uint32_t ap = quad_prev(ak);
-        uint32_t r = ak ^ (ak << 8) ^ (c >> 8) ^ (d << 18);
-        r = xor_and(r, ap >> 24, lo_mask);
-        r = xor_and(r, cn << 24, hi_mask);
+        // (a <<< 8) and (c >>> 8) on this sub-word: a funnel shift with the neighbour's sub-word
+        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak) & lo_mask, 24);
+        const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, 8);
+        uint32_t r = xor3(ak, al, cr);
         r = xor_and(r, bk >> 11, K);
+        r ^= d << 18;
         dst[k * ws + j] = r;
         emit(k, r);
         c = d;
         cn = dn;
         d = r;
-        dn = quad_next(r);
+        dn = quad_next(r) & hi_mask;
     }
 }
 
