@@ -16,7 +16,8 @@
 // work item owns the "column" c, c + (n-m), c + 2(n-m) and carries the
 // dependency in registers: every LDS read is of the old block, every write
 // happens after one barrier. The only cross-column value, new word 0 read by
-// the last word of the block, is recomputed where it is needed.
+// the last word of the block, is published next to the window before that
+// barrier and read after it.
 //
 // Tempering (eq. tempering) and the optional float map are fused between
 // the twist and the 16-byte global store, so each output is written once,
@@ -27,7 +28,12 @@
 // coefficients i of g (Horner's rule unrolled over the word sequence). A
 // workgroup regenerates the raw sequence two blocks at a time in LDS and each
 // wavefront accumulates one lane; the loop over the coefficients of g is
-// wave-uniform (scalar unit), the XORs are VALU.
+// wave-uniform (scalar unit), the XORs are VALU. The reads are the cost (LDS
+// bandwidth), so where LDS allows, coefficients are taken four at a time from
+// derived rows (accumulate_block4).
+//
+// SFMT19937's recurrence is serial along each lane; a quad of threads shares
+// a lane, one 32-bit sub-word each (sfmt_block_quad).
 #include <hip/hip_runtime.h>
 
 #include "vmt_common.hpp"
@@ -308,7 +314,6 @@ struct MtGen {
     // wraps around). It belongs to column C_LAST, in range LAST_R.
     static constexpr int LAST_R = RANGES - 1;
     static constexpr int C_LAST = N - 1 - LAST_R * D;
-    static constexpr size_t LDS_BYTES = sizeof(W) * (N + 1) * LPW;  // window + new word 0
     using VW = Vec<W, V>;
     using Map = OutOf<OUT, W>;
     using OutT = typename Map::T;
@@ -563,14 +568,14 @@ __global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) vo
 }
 
 // ---------------------------------------------------------------------------
-// SFMT generation: one thread per lane runs the lane's serial chain (the
-// recurrence reads the two previous words, Sec. 2.6), lanes in parallel.
+// SFMT generation: a quad of threads per lane runs the lane's serial chain
+// (the recurrence reads the two previous words, Sec. 2.6; sfmt_block_quad),
+// lanes in parallel.
 // ---------------------------------------------------------------------------
 
 template <int LPW, int OUT>
 struct SfmtGen {
     static constexpr int N = kSfmtN, MM = kSfmtM;
-    static constexpr size_t LDS_BYTES = sizeof(uint4) * N * LPW;
     using OutT = typename OutOf<OUT == 0 ? 0 : 1, uint32_t>::T;
 
     static __device__ __forceinline__ OutT map(uint32_t v) {
@@ -742,10 +747,6 @@ __device__ void raw_twist_rows(const typename P::W* src, typename P::W* dst, int
     }
 }
 
-struct SfmtRaw {
-    using W = uint4;
-    static constexpr int N = kSfmtN;
-};
 
 __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int stride, int tid) {
     const int row = tid >> 2, j = tid & 3;  // one quad of threads per row
