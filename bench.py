@@ -43,22 +43,32 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 
 # HBM bytes per launch of the batch kernel from rocprofv3 FETCH_SIZE (x2.0) and
 # WRITE_SIZE (x1.0), scaled by a 4 GiB device copy; valid only for the kernel
-# source and launch shape they were taken with (profiles/batch_mt32_m16_counters.md).
+# code (kernel_fingerprint) and launch shape they were taken with
+# (profiles/batch_mt32_m16_counters.md).
 COUNTERS = {
-    "kernel_sha256": "11d4215ed912c340249c8cab74ad259b5ec10b198092f8c320e7acf662619c42",
+    "kernel_fingerprint": "pending",
     "shape": (512, 16, 2),  # threads per workgroup, store bytes, workgroups per CU
     "read_bytes": 877962880,
     "written_bytes": 96283548139,
 }
 
 
-def counter_traffic(shape) -> int | None:
+def kernel_fingerprint() -> str:
+    """sha256 of the kernel source without comments and whitespace (comment
+    edits do not invalidate counters taken on the same code)."""
     import hashlib
+    import re
 
-    src = os.path.join(ROOT, "paper_2309_16682_amd", "csrc", "vmt_kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != COUNTERS["kernel_sha256"] or (shape.threads, shape.store_bytes, shape.wg_per_cu) != COUNTERS["shape"]:
+    with open(os.path.join(ROOT, "paper_2309_16682_amd", "csrc", "vmt_kernels.hip")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256(re.sub(r"\s+", "", src).encode()).hexdigest()
+
+
+def counter_traffic(shape) -> int | None:
+    if kernel_fingerprint() != COUNTERS["kernel_fingerprint"] or (
+        shape.threads, shape.store_bytes, shape.wg_per_cu) != COUNTERS["shape"]:
         return None
     return COUNTERS["read_bytes"] + COUNTERS["written_bytes"]
 
