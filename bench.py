@@ -484,6 +484,7 @@ def main():
         torch.cuda.empty_cache()
         for name, variant, M, seed, n, kind in (
             ("mt32_M16_2^24_u32", vmt.VMT_MT32, 16, 5489, 1 << 24, "u32"),
+            ("mt32_M1_2^24_u32 (the std::mt19937 stream)", vmt.VMT_MT32, 1, 5489, 1 << 24, "u32"),
             ("mt64_M8_2^26_u64", vmt.VMT_MT64, 8, 5489, 1 << 26, "u64"),
             ("mt64_M8_2^26_f64", vmt.VMT_MT64, 8, 5489, 1 << 26, "f64"),
             ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, "u32"),

@@ -41,6 +41,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2309_16682_amd.build`")
+    try:  # torch first: the library then binds to the HIP runtime torch loaded (one runtime per process)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, I, U32, U64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
     IP = ctypes.POINTER(ctypes.c_int)

@@ -360,3 +360,20 @@ def test_jump_pow2_batch_with_more_distinct_k_than_the_distance_cache(ctx):
         ref = oracle_stream(MT64, M, seed=1 + (i % 3))
         ref.jump(pow2_poly(MT64, i))
         np.testing.assert_array_equal(gen(ctx, states[i], MT64, 700), ref.generate(700), err_msg=f"state {i}")
+
+
+@pytest.mark.parametrize("variant,bits", [(MT32, 32), (MT64, 64)])
+def test_M1_stream_is_the_standard_library_engine(ctx, variant, bits):
+    # a V-generator with one lane is the base generator: std::mt19937 / std::mt19937_64 bit for bit,
+    # in one launch and split over workgroups by jump-ahead
+    n = 300000
+    say(f"case M=1 variant={variant} vs std engine")
+    ref = stdpins.std_stream(bits, 5489, n)
+    for split in (255, 10):
+        native = vmt.VMT_OUT_U64 if variant == MT64 else vmt.VMT_OUT_U32
+        vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, 1, native, lanes_per_wg=1, split_log2=split)
+        try:
+            st = new_init(ctx, variant, 1, 5489)
+            np.testing.assert_array_equal(gen(ctx, st, variant, n), ref, err_msg=f"split {split}")
+        finally:
+            vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, 1, native)
