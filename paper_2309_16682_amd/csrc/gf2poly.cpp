@@ -184,6 +184,79 @@ Words PolyMod::t_pow(const uint64_t* e, size_t e_words) const {
     return acc;
 }
 
+// ---- inverse and square root ----------------------------------------------------
+
+// a ^= b * t^s (a grows as needed)
+static void xor_shifted(Words& a, const Words& b, int s) {
+    const size_t wo = size_t(s) / 64;
+    const int bo = s % 64;
+    if (a.size() < b.size() + wo + 1) a.resize(b.size() + wo + 1, 0);
+    for (size_t j = 0; j < b.size(); j++) {
+        a[j + wo] ^= b[j] << bo;
+        if (bo) a[j + wo + 1] ^= b[j] >> (64 - bo);
+    }
+}
+
+Words PolyMod::inverse(const Words& a) const {
+    // invariant: g1 a = u and g2 a = v (mod mu); deg u + deg v falls at every step
+    Words u = reduce(a), v = mu_, g1(1, 1), g2;
+    poly_trim(u);
+    int du = poly_degree(u), dv = poly_degree(v);
+    if (du < 0) throw std::invalid_argument("inverse of zero");
+    while (du > 0) {
+        int j = du - dv;
+        if (j < 0) {
+            std::swap(u, v);
+            std::swap(g1, g2);
+            std::swap(du, dv);
+            j = -j;
+        }
+        xor_shifted(u, v, j);
+        xor_shifted(g1, g2, j);
+        poly_trim(u);
+        poly_trim(g1);
+        du = poly_degree(u);
+        if (du < 0) throw std::invalid_argument("not invertible modulo mu");
+    }
+    return reduce(g1);
+}
+
+// even / odd coefficients of a 64-bit word, packed into 32 bits each
+static inline uint32_t even_bits(uint64_t x) {
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+// (even part, odd part) of a: a = ae(t^2) + t ao(t^2)
+static void split_even_odd(const Words& a, Words& ae, Words& ao) {
+    const size_t n = (a.size() + 1) / 2;
+    ae.assign(n, 0);
+    ao.assign(n, 0);
+    for (size_t i = 0; i < a.size(); i++) {
+        const uint64_t e = even_bits(a[i]), o = even_bits(a[i] >> 1);
+        ae[i / 2] |= e << (32 * (i % 2));
+        ao[i / 2] |= o << (32 * (i % 2));
+    }
+}
+
+Words PolyMod::sqrt(const Words& a) const {
+    if (sqrt_t_.empty()) {
+        Words me, mo;
+        split_even_odd(mu_, me, mo);
+        sqrt_t_ = mul(me, inverse(mo));
+    }
+    Words ae, ao;
+    split_even_odd(reduce(a), ae, ao);
+    Words r = mul(ao, sqrt_t_);
+    for (size_t i = 0; i < ae.size() && i < r.size(); i++) r[i] ^= ae[i];
+    return r;
+}
+
 // ---- Berlekamp-Massey ---------------------------------------------------------
 
 Words berlekamp_massey(const std::vector<uint8_t>& s) {

@@ -41,9 +41,18 @@ public:
     Words t_pow2(uint64_t k, const Words* start = nullptr) const;  // start^(2^k), start = t by default
     Words t_pow(const uint64_t* e, size_t e_words) const;           // t^e mod mu
 
+    // Inverse modulo mu (extended Euclid); a must be coprime to mu.
+    Words inverse(const Words& a) const;
+    // The square root modulo a square-free mu: a = ae(t^2) + t ao(t^2) gives
+    // sqrt(a) = ae(t) + sqrt(t) ao(t), and sqrt(t) = me(t) / mo(t) for
+    // mu = me(t^2) + t mo(t^2) (since mu(t) = 0). Squaring is a bijection
+    // modulo a square-free mu, so the root is unique.
+    Words sqrt(const Words& a) const;
+
 private:
     Words mu_;
     Words barrett_;  // floor(t^(2D) / mu)
+    mutable Words sqrt_t_;  // sqrt(t) mod mu, computed on first use
     int D_;
     size_t nw_;
 };

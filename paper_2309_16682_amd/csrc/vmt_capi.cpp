@@ -118,11 +118,30 @@ vmt::PolyMod& ring(vmt_ctx* ctx, int variant) {
 }
 
 // t^(2^k) mod mu, extending the cached squaring chain from the nearest k below.
+// MT19937-32/-64: mu is irreducible of degree D = 19937 (2^D - 1, the period,
+// is prime), so t^(2^D) = t (Frobenius): t^(2^k) = t^(2^(k mod D)), and for
+// k mod D close to D it is D - (k mod D) square roots of t -- the lane
+// distances 2^(19937 - log2 M) cost a few square roots instead of ~19,930
+// squarings.
 const Words& pow2(vmt_ctx* ctx, int variant, uint64_t k) {
     auto& cache = ctx->pow2[variant];
     auto it = cache.find(k);
     if (it != cache.end()) return it->second;
     vmt::PolyMod& R = ring(ctx, variant);
+    constexpr uint64_t kD = 19937;
+    if (variant != VMT_SFMT && R.degree() == (int)kD) {
+        const uint64_t e = k % kD;
+        if (e != k) {
+            Words v = pow2(ctx, variant, e);
+            return cache[k] = std::move(v);
+        }
+        if (kD - e <= 64) {
+            Words cur(R.words(), 0);
+            cur[0] = 2;  // t
+            for (uint64_t i = 0; i < kD - e; i++) cur = R.sqrt(cur);
+            return cache[k] = std::move(cur);
+        }
+    }
     auto below = cache.lower_bound(k);
     Words cur;
     uint64_t from = 0;
