@@ -20,8 +20,14 @@
  *     the null stream) and is stream-ordered; results are valid once the
  *     stream has reached the call. Calls return before the GPU work ends.
  *   - Failure: arguments are checked on the host before anything is
- *     enqueued; a call that returns an error has enqueued nothing and left the
- *     state unchanged.
+ *     enqueued; a call that returns an argument error (VMT_EINVAL,
+ *     VMT_EVARIANT, VMT_ESTATE) has enqueued nothing and left the state
+ *     unchanged. After VMT_EDEVICE or VMT_ENOMEM from the HIP runtime part of
+ *     the call's work may have been enqueued: the state is then undefined.
+ *   - Allocation: batched calls, split generation and jumps allocate their
+ *     task lists (and split generation its scratch copies of the state)
+ *     stream-ordered (hipMallocAsync on the call's stream); plans and servers
+ *     allocate once, at creation.
  *   - Concurrency: calls on different states may overlap on different
  *     streams. Calls on one state must be ordered by the caller (one stream).
  *
@@ -122,8 +128,11 @@ int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream);
 int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count,
                         hipStream_t stream);
 
-/* Next n stream elements into d_out (device). generate_u32: MT19937-32 and
- * SFMT19937. generate_u64: MT19937-64. n may be 0. */
+/* Next n stream elements into d_out (device, aligned to the element size).
+ * generate_u32: MT19937-32 and SFMT19937. generate_u64: MT19937-64. n may be
+ * 0. A long call may run split over many workgroups (see "Splitting" below):
+ * the outputs are the same; the state afterwards is the same point of the
+ * stream, possibly on a shifted block grid (as after any jump). */
 int vmt_generate_u32(vmt_ctx* ctx, void* d_state, size_t n, uint32_t* d_out, hipStream_t stream);
 int vmt_generate_u64(vmt_ctx* ctx, void* d_state, size_t n, uint64_t* d_out, hipStream_t stream);
 
