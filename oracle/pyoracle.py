@@ -70,6 +70,8 @@ def lib():
         L.or_poly_sqr_chain.argtypes = [P, P, ctypes.c_uint64, P]
         L.or_poly_powmod_t.argtypes = [P, P, ctypes.c_int, P]
         L.or_poly_gcd.argtypes = [P, P, P]
+        L.or_berlekamp_massey.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t]
+        L.or_berlekamp_massey.restype = ctypes.c_int
         L.or_minpoly.argtypes = [ctypes.c_int, P, P]
         L.or_minpoly.restype = ctypes.c_int
         L.or_jump.argtypes = [ctypes.c_int, P, P]
@@ -148,6 +150,17 @@ def poly_gcd(a: int, b: int) -> int:
     r = np.zeros(OR_PW, np.uint64)
     lib().or_poly_gcd(_ptr(r), _ptr(poly_to_words(a)), _ptr(poly_to_words(b)))
     return words_to_poly(r)
+
+
+def berlekamp_massey(bits: np.ndarray) -> int:
+    """Minimal polynomial (characteristic orientation) of a bit sequence; its
+    degree is the sequence's linear complexity. bits: one bit per element."""
+    s = np.ascontiguousarray(np.asarray(bits) & 1, dtype=np.uint8)
+    pw = s.size // 64 + 2
+    poly = np.zeros(pw, np.uint64)
+    L = lib().or_berlekamp_massey(_ptr(s), s.size, _ptr(poly), pw)
+    assert L >= 0
+    return words_to_poly(poly)
 
 
 def minpoly(variant: int, canon: np.ndarray) -> int:

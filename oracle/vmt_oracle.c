@@ -349,10 +349,61 @@ void or_poly_gcd(uint64_t* r, const uint64_t* a, const uint64_t* b) {
 /* F^d = g(F) with g = t^d mod mu (mu(F) = 0).                              */
 /* ------------------------------------------------------------------------ */
 
+int or_berlekamp_massey(const uint8_t* s, size_t N, uint64_t* poly, size_t poly_words) {
+    const size_t W = N / 64 + 2;
+    /* C: connection polynomial, B: copy before the last length change,
+     * R: reversed window, bit j of R = s_{i-j}. */
+    uint64_t* C = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* B = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* T = (uint64_t*)calloc(W, sizeof(uint64_t));
+    uint64_t* R = (uint64_t*)calloc(W, sizeof(uint64_t));
+    C[0] = 1;
+    B[0] = 1;
+    size_t L = 0, m = 1;
+    for (size_t i = 0; i < N; i++) {
+        for (size_t w = W - 1; w > 0; w--) R[w] = (R[w] << 1) | (R[w - 1] >> 63);
+        R[0] = (R[0] << 1) | (s[i] & 1u);
+        /* discrepancy d = sum_{j=0..L} c_j s_{i-j} */
+        int d = 0;
+        size_t nwords = L / 64 + 1;
+        for (size_t w = 0; w < nwords; w++) d ^= __builtin_parityll(C[w] & R[w]);
+        if (d == 0) {
+            m++;
+            continue;
+        }
+        int grow = 2 * L <= i;
+        if (grow) memcpy(T, C, W * sizeof(uint64_t));
+        /* C := C + t^m B */
+        size_t wo = m >> 6, bo = m & 63;
+        for (size_t w = 0; w + wo < W; w++) {
+            C[w + wo] ^= B[w] << bo;
+            if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
+        }
+        if (grow) {
+            L = i + 1 - L;
+            memcpy(B, T, W * sizeof(uint64_t));
+            m = 1;
+        } else {
+            m++;
+        }
+    }
+    int ok = L < poly_words * 64;
+    if (ok) {
+        /* characteristic orientation: coefficient of t^j is c_{L-j} */
+        memset(poly, 0, poly_words * sizeof(uint64_t));
+        for (size_t j = 0; j <= L; j++)
+            if ((C[(L - j) >> 6] >> ((L - j) & 63)) & 1u) poly[j >> 6] ^= 1ull << (j & 63);
+    }
+    free(C);
+    free(B);
+    free(T);
+    free(R);
+    return ok ? (int)L : -1;
+}
+
 int or_minpoly(int variant, const void* canon, uint64_t* mu) {
     const int maxdeg = 19968;                  /* nw bits: upper bound on deg mu */
     const int N = 2 * maxdeg + 64;             /* terms of the sequence */
-    const int W = (N + 64) / 64 + 1;
     int n = or_state_words(variant), wb = or_word_bytes(variant);
     unsigned char* buf = (unsigned char*)malloc((size_t)n * wb);
     memcpy(buf, canon, (size_t)n * wb);
@@ -373,53 +424,9 @@ int or_minpoly(int variant, const void* canon, uint64_t* mu) {
             s[i] = (uint8_t)(w4[0] & 1u);
         }
     }
-    /* C: connection polynomial, B: copy before the last length change,
-     * R: reversed window, bit j of R = s_{i-j}. */
-    uint64_t* C = (uint64_t*)calloc(W, sizeof(uint64_t));
-    uint64_t* B = (uint64_t*)calloc(W, sizeof(uint64_t));
-    uint64_t* T = (uint64_t*)calloc(W, sizeof(uint64_t));
-    uint64_t* R = (uint64_t*)calloc(W, sizeof(uint64_t));
-    C[0] = 1;
-    B[0] = 1;
-    int L = 0, m = 1;
-    for (int i = 0; i < N; i++) {
-        for (int w = W - 1; w > 0; w--) R[w] = (R[w] << 1) | (R[w - 1] >> 63);
-        R[0] = (R[0] << 1) | s[i];
-        /* discrepancy d = sum_{j=0..L} c_j s_{i-j} */
-        int d = 0;
-        int nwords = L / 64 + 1;
-        for (int w = 0; w < nwords; w++) d ^= __builtin_parityll(C[w] & R[w]);
-        if (d == 0) {
-            m++;
-        } else if (2 * L <= i) {
-            memcpy(T, C, W * sizeof(uint64_t));
-            int wo = m >> 6, bo = m & 63;
-            for (int w = 0; w + wo < W; w++) {
-                C[w + wo] ^= B[w] << bo;
-                if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
-            }
-            L = i + 1 - L;
-            memcpy(B, T, W * sizeof(uint64_t));
-            m = 1;
-        } else {
-            int wo = m >> 6, bo = m & 63;
-            for (int w = 0; w + wo < W; w++) {
-                C[w + wo] ^= B[w] << bo;
-                if (bo && w + wo + 1 < W) C[w + wo + 1] ^= B[w] >> (64 - bo);
-            }
-            m++;
-        }
-    }
-    /* mu(t) = t^L C(1/t): coefficient of t^j is c_{L-j}. */
-    memset(mu, 0, OR_PW * sizeof(uint64_t));
-    for (int j = 0; j <= L; j++)
-        if ((C[(L - j) >> 6] >> ((L - j) & 63)) & 1u) bit_flip(mu, j);
+    int L = or_berlekamp_massey(s, (size_t)N, mu, OR_PW);
     free(buf);
     free(s);
-    free(C);
-    free(B);
-    free(T);
-    free(R);
     return L;
 }
 

@@ -82,6 +82,13 @@ void or_poly_sqr_chain(uint64_t* r, const uint64_t* start, uint64_t k, const uin
 void or_poly_powmod_t(uint64_t* r, const uint64_t* e, int e_words, const uint64_t* mu);
 void or_poly_gcd(uint64_t* r, const uint64_t* a, const uint64_t* b);
 
+/* Minimal polynomial (shortest linear recurrence) of an arbitrary bit
+ * sequence s[0..N-1] (one bit per byte, bit 0 used) by Berlekamp-Massey, in
+ * characteristic orientation: sum_j poly_j s_{i+j} = 0 for every i with
+ * i + L < N, L its degree = the linear complexity of the sequence. poly has
+ * poly_words words; returns L, or -1 if L does not fit. */
+int or_berlekamp_massey(const uint8_t* s, size_t N, uint64_t* poly, size_t poly_words);
+
 /* Minimal polynomial of the bit sequence (bit 0 of sub-word 0 of each new raw
  * word) produced from the canonical state, by Berlekamp-Massey over
  * 2*maxdeg+64 terms. Returns its degree. */
