@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving section only")
+    ap.add_argument("--only-check", action="store_true", help="run the linear-complexity self-check section only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch the rounds eagerly instead of replaying a graph")
     ap.add_argument("--tune-sample", type=int, default=8192)
@@ -196,6 +197,48 @@ def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
     return out
 
 
+# VALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3 T lane-ops/s; one
+# three-input XOR (v_bitop3_b32) folds two terms of the recurrence, so at most 78.6 T term-XORs/s.
+CHECK_PEAK_TERMS = 2 * 256 * 4 * 16 * 2.4e9
+
+
+def self_check(ctx, torch, reps: int = 3) -> dict:
+    """Time vmt_check_stream on single streams: term-XORs = set coefficients x checked offsets."""
+    from paper_2309_16682_amd import vmt
+
+    res = {}
+    for name, variant, M, seed, n, kind, esz, wpe, S in (
+        ("mt32_M16_2^24_u32", vmt.VMT_MT32, 16, 5489, 1 << 24, vmt.VMT_OUT_U32, 4, 1, 1),
+        ("mt64_M8_2^26_u64", vmt.VMT_MT64, 8, 5489, 1 << 26, vmt.VMT_OUT_U64, 8, 2, 2),
+        ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, vmt.VMT_OUT_U32, 4, 1, 4),
+    ):
+        A = vmt.vmt_check_poly(ctx, variant, M)
+        deg, terms = A.bit_length() - 1, bin(A).count("1")
+        st = vmt.new_state(variant, M)
+        vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+        out = torch.empty(n * esz, dtype=torch.uint8, device="cuda")
+        (vmt.vmt_generate_u64 if esz == 8 else vmt.vmt_generate_u32)(ctx, st, n, out)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        stream = torch.cuda.current_stream()
+        vmt.vmt_check_stream(ctx, variant, M, kind, out, n, cnt, stream=stream)  # uploads A, warms up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            vmt.vmt_check_stream(ctx, variant, M, kind, out, n, cnt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        nw = n * wpe
+        offsets = nw - deg * S
+        rate = terms * offsets / sec
+        res[name] = {"failing_offsets": int(cnt.item()), "words": nw, "ms": round(sec * 1e3, 3),
+                     "Gwords_per_s": round(nw / sec / 1e9, 3), "set_coefficients": terms,
+                     "term_xors_per_s": float(f"{rate:.4g}"), "frac_of_xor_peak": round(rate / CHECK_PEAK_TERMS, 3)}
+        log(f"self-check {name}: {res[name]}")
+        del out
+    return res
+
+
 def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chunk: int = 1 << 20) -> dict:
     """Serving configuration: 4096 device-resident V-MT19937-64 (M = 8)
     states seeded init_genrand(i + 1); Poisson arrivals at 20k requests/s,
@@ -281,6 +324,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.calibrate:
         print(json.dumps(calibrate(torch)), flush=True)
+        return
+    if args.only_check:
+        ctx = vmt.vmt_ctx_create(0)
+        print(json.dumps({"self_check": self_check(ctx, torch)}), flush=True)
+        vmt.vmt_ctx_destroy(ctx)
         return
     if args.only_serving:
         ctx = vmt.vmt_ctx_create(0)
@@ -523,6 +571,7 @@ def main():
             log(f"{name}: {sec[name]}")
             del out
         result["single_stream"] = sec
+        result["self_check"] = self_check(ctx, torch)
 
     arena = out_base = None  # the batch arena is not needed any more
     torch.cuda.empty_cache()

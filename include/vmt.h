@@ -238,6 +238,50 @@ int vmt_minpoly(vmt_ctx* ctx, int variant, uint64_t* out, size_t cap, int* degre
 int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dist_words, uint64_t* out,
                   size_t cap, int* degree);
 
+/* ---- linear-complexity self-check ----------------------------------------------
+ * Every output bit of an F2-linear generator, read along its stream, obeys a
+ * fixed linear recurrence; its length is the sequence's linear complexity,
+ * which the paper reports as the one statistical test every MT-based
+ * generator fails (Sec. 4, LinearComp). For the V-stream the recurrence is
+ * known in closed form, so a generated buffer can be checked against it on
+ * the device at any size:
+ *
+ *   MT19937-32/-64: A = mu, the minimal polynomial (irreducible, degree
+ *     19937). Lane t is lane 0 advanced t J steps with J = 2^(19937 - log2 M);
+ *     since alpha^(2^19937) = alpha for every root alpha of mu, the
+ *     interleaved bit sequence is again a trace sequence of a root of mu (a
+ *     conjugate), so each bit of the V-stream obeys mu itself: the linear
+ *     complexity stays 19937 for every M (eq. combseq). Any other lane spacing
+ *     gives 19937 M.
+ *   SFMT19937: mu = phi psi with phi of degree 19937 (the period part) and psi
+ *     of degree 31; the phi part collapses as above, the psi part does not, so
+ *     each bit of the sequence of 128-bit words obeys A = phi(t) psi(t^M)
+ *     (degree 19937 + 31 M).
+ *
+ * vmt_check_poly writes A (bit i of out = coefficient of t^i; cap words
+ * available) and its degree; host only. */
+int vmt_check_poly(vmt_ctx* ctx, int variant, uint32_t M, uint64_t* out, size_t cap, int* degree);
+
+/* Count the offsets at which a generated stream breaks its recurrence. The
+ * stream (n elements of out_kind, as the generate, uniform or batch calls
+ * write them for this variant and M) is read as the sequence w of 32-bit
+ * words it carries: uint32 as is, float as its integer f 2^24, uint64 as
+ * (low, high) halves, double as the halves of its integer f 2^53. With
+ * S = words per recurrence step (MT19937-32: 1 (u32, f32); MT19937-64: 2
+ * (u64, f64), 1 (f32); SFMT19937: 4 (u32, f32), one 128-bit word), every
+ * offset x with x + deg(A) S < n_words must satisfy
+ * XOR_{i : A_i = 1} w[x + i S] = 0. *d_count (one uint64 in device memory,
+ * overwritten) receives the number of offsets where it does not: 0 for an
+ * intact stream; a single flipped bit gives one failing offset per set
+ * coefficient of A within range, a wrong lane spacing almost every offset.
+ * The stream may start anywhere in the V-stream. Enqueued on `stream`;
+ * VMT_EINVAL if n_words <= deg(A) S (nothing to check), VMT_EVARIANT for an
+ * out kind the variant does not produce (u64 or f64 of the 32-bit
+ * generators). Allocates nothing after the first call for a (variant, M):
+ * the device copy of A stays with the context. */
+int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const void* d_out, uint64_t n,
+                     uint64_t* d_count, hipStream_t stream);
+
 /* ---- launch shapes and the autotuner ------------------------------------------
  * Family VMT_FAMILY_GENERATE is generation from one state (vmt_generate_*,
  * vmt_uniform_*): the state's M lanes are split over M / lanes_per_wg

@@ -22,7 +22,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["gf2poly.cpp", "vmt_capi.cpp", "vmt_serve.cpp", "vmt_tune.cpp"]
-HIP_SOURCES = ["vmt_kernels.hip"]
+HIP_SOURCES = ["vmt_kernels.hip", "vmt_check.hip"]
 HIP_FLAGS = [
     "-O3",
     "-std=c++17",

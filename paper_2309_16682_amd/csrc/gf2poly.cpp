@@ -197,6 +197,36 @@ static void xor_shifted(Words& a, const Words& b, int s) {
     }
 }
 
+// ---- gcd and division (schoolbook: used once per table, not per call) ------------
+
+Words poly_div(const Words& a, const Words& b, Words* rem) {
+    const int db = poly_degree(b);
+    if (db < 0) throw std::invalid_argument("division by zero");
+    Words r = a, q;
+    poly_trim(r);
+    for (int dr = poly_degree(r); dr >= db; dr = poly_degree(r)) {
+        const int s = dr - db;
+        if (q.size() <= size_t(s) / 64) q.resize(size_t(s) / 64 + 1, 0);
+        q[size_t(s) / 64] ^= 1ull << (s % 64);
+        xor_shifted(r, b, s);
+        poly_trim(r);
+    }
+    if (rem) *rem = r;
+    return q;
+}
+
+Words poly_gcd(Words a, Words b) {
+    poly_trim(a);
+    poly_trim(b);
+    while (poly_degree(b) >= 0) {
+        Words r;
+        poly_div(a, b, &r);
+        a = std::move(b);
+        b = std::move(r);
+    }
+    return a;
+}
+
 Words PolyMod::inverse(const Words& a) const {
     // invariant: g1 a = u and g2 a = v (mod mu); deg u + deg v falls at every step
     Words u = reduce(a), v = mu_, g1(1, 1), g2;

@@ -26,6 +26,12 @@ void poly_trim(Words& a);
 // Full (unreduced) product.
 Words poly_mul(const Words& a, const Words& b);
 
+// Greatest common divisor (monic, as every nonzero polynomial over GF(2)).
+Words poly_gcd(Words a, Words b);
+
+// Quotient a / b; *rem (optional) receives the remainder. b must be nonzero.
+Words poly_div(const Words& a, const Words& b, Words* rem = nullptr);
+
 // Arithmetic modulo a fixed polynomial mu of degree D >= 64.
 class PolyMod {
 public:

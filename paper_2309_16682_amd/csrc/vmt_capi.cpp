@@ -72,6 +72,13 @@ struct LaneTable {
     uint32_t max_deg = 0;
 };
 
+// Recurrence polynomial of each bit of a V-stream (linear-complexity check).
+struct CheckPoly {
+    Words host;
+    uint32_t deg = 0;
+    uint32_t* d = nullptr;  // deg + 1 bits as uint32 words, zero-padded to kCheckChunkBits
+};
+
 }  // namespace
 
 struct vmt_ctx {
@@ -86,6 +93,7 @@ struct vmt_ctx {
                                                          // servers and batches hold these pointers)
     std::map<uint32_t, vmt_shape> shapes;  // shape_key -> launch shape set by the caller or the autotuner
     std::map<uint32_t, SplitTable> split[3];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
+    std::map<uint32_t, CheckPoly> check[3];   // M -> recurrence polynomial of the V-stream's bits
     std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
 };
 
@@ -172,6 +180,36 @@ int upload_poly(const Words& p, DevPoly* out) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(poly)");
     out->deg = deg < 0 ? 0 : uint32_t(deg);
     return VMT_OK;
+}
+
+// Recurrence polynomial A of every bit of the V-stream of M lanes (caller
+// holds ctx->mu). Lane t starts t J steps after lane 0, J = 2^(19937 - log2 M)
+// (Sec. 3). For a root alpha of the degree-19937 factor phi of mu,
+// alpha^(2^19937) = alpha, so alpha^J is the M-th root of alpha: the
+// interleaved sequence of a bit is a trace sequence of alpha^J, a conjugate
+// of alpha, and obeys phi again. MT19937: mu = phi, A = mu. SFMT19937:
+// mu = phi psi (psi of degree 31); the psi part of lane t is a sequence of
+// psi shifted by t J, the interleave of M of them obeys psi(t^M) = psi^M,
+// so A = phi psi^M for the sequence of 128-bit words.
+CheckPoly& check_poly(vmt_ctx* ctx, int variant, uint32_t M) {
+    auto it = ctx->check[variant].find(M);
+    if (it != ctx->check[variant].end()) return it->second;
+    vmt::PolyMod& R = ring(ctx, variant);
+    Words A = R.modulus();
+    if (variant == VMT_SFMT) {
+        Words f = pow2(ctx, variant, 19937);  // t^(2^19937) mod mu
+        f[0] ^= 2;                            // - t
+        const Words phi = vmt::poly_gcd(R.modulus(), f);
+        Words rem;
+        Words psiM = vmt::poly_div(R.modulus(), phi, &rem);
+        for (uint32_t m = 1; m < M; m *= 2) psiM = vmt::poly_mul(psiM, psiM);
+        A = vmt::poly_mul(phi, psiM);
+    }
+    vmt::poly_trim(A);
+    CheckPoly& c = ctx->check[variant][M];
+    c.host = A;
+    c.deg = (uint32_t)vmt::poly_degree(A);
+    return c;
 }
 
 // Lane polynomials t^(t J) mod mu, t = 0..M-1, J = 2^(19937 - log2 M) (Sec. 3, Table jvalues).
@@ -649,6 +687,7 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
             for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->pow2_dev[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->split[v]) (void)hipFree(kv.second.d);
+            for (auto& kv : ctx->check[v]) (void)hipFree(kv.second.d);
         }
         for (void* p : ctx->retired) (void)hipFree(p);
     }
@@ -967,6 +1006,71 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
     std::fill(out, out + cap, 0);
     std::copy(g.begin(), g.end(), out);
     if (degree) *degree = vmt::poly_degree(g);
+    return VMT_OK;
+}
+
+int vmt_check_poly(vmt_ctx* ctx, int variant, uint32_t M, uint64_t* out, size_t cap, int* degree) {
+    if (!ctx || !out) return fail(VMT_EINVAL, "null argument");
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const CheckPoly& c = check_poly(ctx, variant, M);
+    if (cap < c.host.size()) return fail(VMT_EINVAL, "need %zu words", c.host.size());
+    std::fill(out, out + cap, 0);
+    std::copy(c.host.begin(), c.host.end(), out);
+    if (degree) *degree = (int)c.deg;
+    return VMT_OK;
+}
+
+int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const void* d_out, uint64_t n,
+                     uint64_t* d_count, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    if (!d_out || !d_count) return fail(VMT_EINVAL, "null argument");
+    if (out_kind < VMT_OUT_U32 || out_kind > VMT_OUT_F64) return fail(VMT_EINVAL, "unknown output kind %d", out_kind);
+    // 32-bit words per element and per recurrence step (one base-generator word)
+    const bool wide = out_kind == VMT_OUT_U64 || out_kind == VMT_OUT_F64;
+    if (variant != VMT_MT64 && wide)
+        return fail(VMT_EVARIANT, "variant %d produces no 64-bit output kind %d", variant, out_kind);
+    const uint32_t wpe = wide ? 2 : 1;
+    const uint32_t S = variant == VMT_SFMT ? 4 : wpe;
+    if ((uintptr_t)d_out % (4 * wpe) || (uintptr_t)d_count % 8)
+        return fail(VMT_EINVAL, "misaligned stream or count pointer");
+    if (n > (UINT64_MAX >> 2)) return fail(VMT_EINVAL, "stream too long");
+    const uint64_t nw = n * wpe;
+    const uint32_t* d_A = nullptr;
+    uint32_t deg = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        CheckPoly& c = check_poly(ctx, variant, M);
+        deg = c.deg;
+        if (nw <= (uint64_t)deg * S)
+            return fail(VMT_EINVAL, "stream of %llu words is too short for a recurrence of degree %u (stride %u)",
+                        (unsigned long long)nw, deg, S);
+        if (!c.d) {
+            const size_t bits = ((size_t)deg + vmt::kCheckChunkBits) / vmt::kCheckChunkBits * vmt::kCheckChunkBits;
+            std::vector<uint32_t> words(bits / 32, 0);
+            for (size_t i = 0; i < c.host.size() && 2 * i < words.size(); i++) {
+                words[2 * i] = (uint32_t)c.host[i];
+                if (2 * i + 1 < words.size()) words[2 * i + 1] = (uint32_t)(c.host[i] >> 32);
+            }
+            void* d = nullptr;
+            hipError_t e = hipMalloc(&d, words.size() * 4);
+            if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(check polynomial): %s", hipGetErrorString(e));
+            e = hipMemcpy(d, words.data(), words.size() * 4, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                return hip_fail(e, "hipMemcpy(check polynomial)");
+            }
+            c.d = static_cast<uint32_t*>(d);
+        }
+        d_A = c.d;
+    }
+    hipError_t e = vmt::launch_check(out_kind, d_out, nw, S, d_A, deg, reinterpret_cast<unsigned long long*>(d_count),
+                                     8 * vmt::device_cus(ctx->device), stream);
+    if (e != hipSuccess) return hip_fail(e, "check kernel launch");
     return VMT_OK;
 }
 

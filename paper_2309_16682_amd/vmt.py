@@ -73,6 +73,8 @@ def lib():
         "vmt_state_release": ([P, P], I),
         "vmt_minpoly": ([P, I, P, SZ, IP], I),
         "vmt_jump_poly": ([P, I, P, SZ, P, SZ, IP], I),
+        "vmt_check_poly": ([P, I, U32, P, SZ, IP], I),
+        "vmt_check_stream": ([P, I, U32, I, P, U64, P, P], I),
         "vmt_shape_get": ([P, I, I, U32, I, P], I),
         "vmt_shape_set": ([P, I, I, U32, I, P], I),
         "vmt_autotune": ([P, I, I, U32, I, P, SZ, I, P, P, SZ, ctypes.POINTER(SZ), P], I),
@@ -94,8 +96,8 @@ def exported_symbols() -> list:
         "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
         "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
-        "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_shape_get",
-        "vmt_shape_set", "vmt_autotune",
+        "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_check_poly",
+        "vmt_check_stream", "vmt_shape_get", "vmt_shape_set", "vmt_autotune",
         "vmt_server_create", "vmt_server_run", "vmt_server_destroy",
     ]
 
@@ -261,6 +263,20 @@ def vmt_minpoly(ctx, variant) -> int:
     deg = ctypes.c_int(0)
     _check(lib().vmt_minpoly(ctx, variant, out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(deg)))
     return int.from_bytes(out.tobytes(), "little")
+
+
+def vmt_check_poly(ctx, variant, M) -> int:
+    """Recurrence polynomial of every bit of the V-stream (as a Python int)."""
+    out = np.zeros(400, np.uint64)
+    deg = ctypes.c_int(0)
+    _check(lib().vmt_check_poly(ctx, variant, M, out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(deg)))
+    return int.from_bytes(out.tobytes(), "little")
+
+
+def vmt_check_stream(ctx, variant, M, out_kind, d_out, n, d_count, stream=None):
+    """Enqueue the recurrence check of n elements of d_out; the number of
+    failing offsets lands in d_count (one int64 on the device)."""
+    return _check(lib().vmt_check_stream(ctx, variant, M, out_kind, _dptr(d_out), n, _dptr(d_count), _stream(stream)))
 
 
 def vmt_jump_poly(ctx, variant, distance: int) -> int:
