@@ -197,9 +197,12 @@ def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
     return out
 
 
-# VALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3 T lane-ops/s; one
-# three-input XOR (v_bitop3_b32) folds two terms of the recurrence, so at most 78.6 T term-XORs/s.
+# Ceilings of the self-check kernel. Dense form: VALU issue, 256 CUs x 4 SIMDs x 16 lanes per clock x
+# 2.4 GHz = 39.3 T lane-ops/s, and one three-input XOR (v_bitop3_b32) folds two terms of the
+# recurrence: at most 78.6 T term-XORs/s. Sparse form: every term of every offset reads one 4-byte
+# word from LDS, 256 CUs x 128 B/clock x 2.4 GHz = 78.6 TB/s.
 CHECK_PEAK_TERMS = 2 * 256 * 4 * 16 * 2.4e9
+LDS_PEAK_BYTES = 256 * 128 * 2.4e9
 
 
 def self_check(ctx, torch, reps: int = 3) -> dict:
@@ -231,9 +234,18 @@ def self_check(ctx, torch, reps: int = 3) -> dict:
         nw = n * wpe
         offsets = nw - deg * S
         rate = terms * offsets / sec
+        dense = terms * 8 > deg  # the library's choice of form
         res[name] = {"failing_offsets": int(cnt.item()), "words": nw, "ms": round(sec * 1e3, 3),
                      "Gwords_per_s": round(nw / sec / 1e9, 3), "set_coefficients": terms,
-                     "term_xors_per_s": float(f"{rate:.4g}"), "frac_of_xor_peak": round(rate / CHECK_PEAK_TERMS, 3)}
+                     "form": "dense" if dense else "sparse", "term_xors_per_s": float(f"{rate:.4g}")}
+        if dense:
+            res[name]["roofline"] = {"bound": "alu", "achieved": float(f"{rate / 1e12:.4g}"),
+                                     "peak": CHECK_PEAK_TERMS / 1e12, "unit": "T term-XORs/s",
+                                     "frac": round(rate / CHECK_PEAK_TERMS, 3)}
+        else:
+            lds = 4 * rate
+            res[name]["roofline"] = {"bound": "lds", "achieved": round(lds / 1e9, 1), "peak": LDS_PEAK_BYTES / 1e9,
+                                     "unit": "GB/s", "frac": round(lds / LDS_PEAK_BYTES, 3)}
         log(f"self-check {name}: {res[name]}")
         del out
     return res

@@ -76,7 +76,8 @@ struct LaneTable {
 struct CheckPoly {
     Words host;
     uint32_t deg = 0;
-    uint32_t* d = nullptr;  // deg + 1 bits as uint32 words, zero-padded to kCheckChunkBits
+    uint32_t* d = nullptr;  // one device block: bit pattern, coefficient list, chunk offsets
+    vmt::CheckPolyDev dev;
 };
 
 }  // namespace
@@ -1040,7 +1041,7 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
         return fail(VMT_EINVAL, "misaligned stream or count pointer");
     if (n > (UINT64_MAX >> 2)) return fail(VMT_EINVAL, "stream too long");
     const uint64_t nw = n * wpe;
-    const uint32_t* d_A = nullptr;
+    vmt::CheckPolyDev dev;
     uint32_t deg = 0;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1050,25 +1051,43 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
             return fail(VMT_EINVAL, "stream of %llu words is too short for a recurrence of degree %u (stride %u)",
                         (unsigned long long)nw, deg, S);
         if (!c.d) {
-            const size_t bits = ((size_t)deg + vmt::kCheckChunkBits) / vmt::kCheckChunkBits * vmt::kCheckChunkBits;
-            std::vector<uint32_t> words(bits / 32, 0);
-            for (size_t i = 0; i < c.host.size() && 2 * i < words.size(); i++) {
-                words[2 * i] = (uint32_t)c.host[i];
-                if (2 * i + 1 < words.size()) words[2 * i + 1] = (uint32_t)(c.host[i] >> 32);
+            // bit pattern (dense form) and set coefficients with per-chunk offsets (sparse form)
+            const uint32_t C = vmt::kCheckChunkBits;
+            const size_t n_bitw = ((size_t)deg + C) / C * C / 32;
+            std::vector<uint32_t> blob(n_bitw, 0), terms, off;
+            for (size_t i = 0; i < c.host.size() && 2 * i < n_bitw; i++) {
+                blob[2 * i] = (uint32_t)c.host[i];
+                if (2 * i + 1 < n_bitw) blob[2 * i + 1] = (uint32_t)(c.host[i] >> 32);
             }
+            for (uint32_t ch = 0; ch <= deg / C; ch++) {
+                off.push_back((uint32_t)terms.size());
+                for (uint32_t i = ch * C; i < (ch + 1) * C && i <= deg; i++)
+                    if ((blob[i / 32] >> (i % 32)) & 1u) terms.push_back(i);
+            }
+            off.push_back((uint32_t)terms.size());
+            const size_t at_terms = blob.size(), at_off = at_terms + terms.size();
+            blob.insert(blob.end(), terms.begin(), terms.end());
+            blob.insert(blob.end(), off.begin(), off.end());
             void* d = nullptr;
-            hipError_t e = hipMalloc(&d, words.size() * 4);
+            hipError_t e = hipMalloc(&d, blob.size() * 4);
             if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(check polynomial): %s", hipGetErrorString(e));
-            e = hipMemcpy(d, words.data(), words.size() * 4, hipMemcpyHostToDevice);
+            e = hipMemcpy(d, blob.data(), blob.size() * 4, hipMemcpyHostToDevice);
             if (e != hipSuccess) {
                 (void)hipFree(d);
                 return hip_fail(e, "hipMemcpy(check polynomial)");
             }
             c.d = static_cast<uint32_t*>(d);
+            c.dev.deg = deg;
+            // Sparse costs one LDS word per coefficient and offset, dense one 40-word window per 32
+            // coefficients (8 offsets) plus the XORs: the coefficient list wins below ~4 per 32.
+            c.dev.dense = terms.size() * 8 > (size_t)deg;
+            c.dev.bits = c.d;
+            c.dev.terms = c.d + at_terms;
+            c.dev.term_off = c.d + at_off;
         }
-        d_A = c.d;
+        dev = c.dev;
     }
-    hipError_t e = vmt::launch_check(out_kind, d_out, nw, S, d_A, deg, reinterpret_cast<unsigned long long*>(d_count),
+    hipError_t e = vmt::launch_check(out_kind, d_out, nw, S, dev, reinterpret_cast<unsigned long long*>(d_count),
                                      8 * vmt::device_cus(ctx->device), stream);
     if (e != hipSuccess) return hip_fail(e, "check kernel launch");
     return VMT_OK;

@@ -1,4 +1,4 @@
-// vmt_check.hip -- gfx950 kernel of the linear-complexity self-check.
+// vmt_check.hip -- gfx950 kernels of the linear-complexity self-check.
 //
 // Every output bit of an F2-linear generator, read along its stream, obeys
 // the linear recurrence of a polynomial A (Sec. 4 reports the resulting
@@ -7,23 +7,31 @@
 // for every offset x, XOR over the set coefficients i of A of the 32-bit
 // words w[x + i S] must be zero.
 //
-// The work is a correlation of the word sequence with the bit pattern of A
-// (about deg(A) / 2 ~ 10^4 set coefficients): plain integer ALU work, about
-// 10^4 XORs per stream word, bound by the VALU and by LDS reads. No MFMA:
-// the arithmetic is over GF(2).
+// The work is a correlation of the word sequence with the coefficient
+// pattern of A: plain integer ALU and LDS work (no MFMA: the arithmetic is
+// over GF(2)). The S phases of the stride are independent sequences; a
+// workgroup takes a tile of kTile consecutive offsets of one phase and
+// stages the phase's words in LDS in chunks of kChunk coefficients
+// (kTile + kChunk words), the next chunk's global loads in flight while the
+// current chunk is worked on. Two forms, chosen by the density of A:
 //
-// Mapping. The S phases of the stride are independent sequences; a
-// workgroup takes a tile of kTile consecutive offsets of one phase, thread t
-// the kR = 8 consecutive offsets kR t .. kR t + 7. The phase's words are
-// staged in LDS in chunks of kChunk coefficients (kTile + kChunk words). For
-// each 32-coefficient word of A (a wave-uniform scalar load) a thread reads
-// its window of kR + 32 words with ds_read_b128 and, nibble by nibble, XORs
-// the selected window words into its accumulators: the nibble's value picks
-// one of 16 straight-line cases (a scalar branch), each combining up to four
-// words per accumulator with three-input XORs, ~1.25 VALU ops per nibble and
-// accumulator on average. LDS layout: word j sits in plane (j / 4) % 2 at
-// 16-byte slot j / 8, so the window (five 8-word groups) is ten 16-byte
-// reads at a 16-byte lane stride: no bank conflicts.
+// Sparse (MT19937-32/-64: mu has 135 / 285 set coefficients of 19,938).
+// Thread t owns the offsets t + kThreads r, r < kR. For each set coefficient
+// i (a wave-uniform list) it XORs buf[i + t + kThreads r] into accumulator r:
+// consecutive lanes read consecutive words (conflict-free ds_read_b32), two
+// coefficients per three-input XOR. Every LDS byte read is used: the bound
+// is LDS bandwidth, 4 bytes per coefficient and offset.
+//
+// Dense (SFMT19937: phi psi^M has ~9,300 set coefficients). Thread t owns the
+// kR consecutive offsets kR t .. kR t + kR - 1, so one LDS window of kR + 32
+// words serves 32 coefficients. For each 32-coefficient word of A (a scalar
+// load, the next one in flight) a thread reads its window with ten
+// ds_read_b128 and, nibble by nibble, XORs the selected window words into its
+// accumulators: the nibble's value picks one of 16 straight-line cases (a
+// scalar branch), each combining up to four words per accumulator with
+// three-input XORs, ~1.25 VALU ops per nibble and accumulator. LDS layout:
+// word j sits in plane (j / 4) % 2 at 16-byte slot j / 8, so the window (five
+// 8-word groups) is ten 16-byte reads at a 16-byte lane stride.
 #include <hip/hip_runtime.h>
 
 #include "vmt_launch.hpp"
@@ -31,30 +39,30 @@
 namespace vmt {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kR = 8;                     // consecutive offsets per thread
+constexpr int kThreads = 512;
+constexpr int kR = 8;                     // offsets per thread
 constexpr int kTile = kThreads * kR;      // offsets per workgroup tile
 constexpr int kChunk = kCheckChunkBits;   // coefficients staged per LDS fill
 constexpr int kBuf = kTile + kChunk;      // LDS words per fill
-constexpr int kWin = kR + 32;             // window words per 32 coefficients
-static_assert(kChunk % 32 == 0 && kR == 8 && kBuf % 8 == 0, "window = 8-word groups");
+constexpr int kPer = kBuf / kThreads;     // staged words per thread
+constexpr int kWin = kR + 32;             // dense window: words per 32 coefficients
+static_assert(kChunk % 32 == 0 && kR == 8 && kBuf % (4 * kThreads) == 0, "staging in 16-byte groups");
 
-// LDS slot of buffer word j: two planes of 4-word groups.
-__device__ __forceinline__ uint32_t lds_slot(uint32_t j) {
-    return ((j >> 2) & 1) * (kBuf / 2) + (j >> 3) * 4 + (j & 3);
-}
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // a ^ b ^ c in one VALU op (v_bitop3_b32, truth table 0x96)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, (unsigned char)0x96);
 }
 
+// ---- dense form: nibble cases ---------------------------------------------------
+
 // acc[r] ^= XOR over the set bits e of V of w[e + r], r < kR.
 template <int V>
 __device__ __forceinline__ void nibble(uint32_t (&acc)[kR], const uint32_t* w) {
     constexpr int n = __builtin_popcount(V);
-    constexpr int e0 = V & 1 ? 0 : V & 2 ? 1 : V & 4 ? 2 : 3;           // lowest set bit
-    constexpr int e3 = V & 8 ? 3 : V & 4 ? 2 : V & 2 ? 1 : 0;           // highest set bit
+    constexpr int e0 = V & 1 ? 0 : V & 2 ? 1 : V & 4 ? 2 : 3;                    // lowest set bit
+    constexpr int e3 = V & 8 ? 3 : V & 4 ? 2 : V & 2 ? 1 : 0;                    // highest set bit
     constexpr int e1 = (V & ~(1 << e0)) & 2 ? 1 : (V & ~(1 << e0)) & 4 ? 2 : 3;  // second lowest
 #pragma unroll
     for (int r = 0; r < kR; r++) {
@@ -91,7 +99,12 @@ __device__ __forceinline__ void apply_nibble(uint32_t v, uint32_t (&acc)[kR], co
     }
 }
 
-__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// Dense LDS slot of buffer word j: two planes of 4-word groups.
+__device__ __forceinline__ uint32_t dense_slot(uint32_t j) {
+    return ((j >> 2) & 1) * (kBuf / 2) + (j >> 3) * 4 + (j & 3);
+}
+
+// ---- staging -------------------------------------------------------------------
 
 // Word X of the stream: uint32 as is, float as its integer f 2^24, uint64 and
 // double (f 2^53) as (low, high) halves. Both float maps are exact.
@@ -109,20 +122,77 @@ __device__ __forceinline__ uint32_t stream_word(const void* src, uint64_t X) {
     }
 }
 
+// Words base + j, j < kBuf, of phase p, held in registers between the global
+// loads and the LDS stores. Thread t takes the 4-word groups
+// j = 4 (t + kThreads m): with S == 1, 32-bit elements and a 16-byte aligned
+// stream a group is one 16-byte load (base is a multiple of 4), otherwise
+// four word loads. Words at or beyond nk read as 0.
+template <int KIND>
+struct Stage {
+    uint32_t v[kPer];
+
+    __device__ __forceinline__ void fetch(const void* src, bool vec, uint32_t p, uint32_t S, uint64_t base,
+                                          uint64_t nk, uint32_t t) {
+#pragma unroll
+        for (int m = 0; m < kPer / 4; m++) {
+            const uint64_t k = base + 4 * (t + kThreads * m);
+            if constexpr (KIND == kOutU32 || KIND == kOutF32) {
+                if (vec && k + 3 < nk) {
+                    const uint4 u = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(src) + k);
+                    if constexpr (KIND == kOutU32) {
+                        v[4 * m] = u.x;
+                        v[4 * m + 1] = u.y;
+                        v[4 * m + 2] = u.z;
+                        v[4 * m + 3] = u.w;
+                    } else {
+                        v[4 * m] = (uint32_t)(__uint_as_float(u.x) * 16777216.0f);
+                        v[4 * m + 1] = (uint32_t)(__uint_as_float(u.y) * 16777216.0f);
+                        v[4 * m + 2] = (uint32_t)(__uint_as_float(u.z) * 16777216.0f);
+                        v[4 * m + 3] = (uint32_t)(__uint_as_float(u.w) * 16777216.0f);
+                    }
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[4 * m + e] = k + e < nk ? stream_word<KIND>(src, p + (k + e) * S) : 0u;
+        }
+    }
+
+    // The four words of a group are adjacent (and 16-byte aligned) in both layouts.
+    template <bool DENSE>
+    __device__ __forceinline__ void store(uint32_t* buf, uint32_t t) const {
+#pragma unroll
+        for (int m = 0; m < kPer / 4; m++) {
+            const uint32_t j = 4 * (t + kThreads * m);
+            *reinterpret_cast<uint4*>(buf + (DENSE ? dense_slot(j) : j)) =
+                make_uint4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
+        }
+    }
+};
+
 __global__ void zero_count_kernel(unsigned long long* count) { *count = 0; }
 
-// nw words in S phases; phase p holds words p, p + S, ...; A: deg + 1
-// coefficients as uint32 words, zero-padded to a multiple of kChunk.
-template <int KIND>
+// ---- the kernel -----------------------------------------------------------------
+
+// nw words in S phases; phase p holds words p, p + S, .... Dense: A = deg + 1
+// coefficients as uint32 words, zero-padded to a multiple of kChunk bits.
+// Sparse: E = the set coefficients in increasing order, E[Eoff[c] ..
+// Eoff[c + 1]) those of chunk c = [c kChunk, (c + 1) kChunk).
+template <int KIND, bool DENSE>
 __global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict__ src, uint64_t nw, uint32_t S,
-                                                        const uint32_t* __restrict__ A, uint32_t deg,
+                                                        const uint32_t* __restrict__ A,
+                                                        const uint32_t* __restrict__ E,
+                                                        const uint32_t* __restrict__ Eoff, uint32_t deg,
                                                         uint64_t tiles_per_phase, unsigned long long* count) {
     __shared__ __align__(16) uint32_t buf[kBuf];
     __shared__ unsigned long long wg_count;
     const uint32_t t = threadIdx.x;
     if (t == 0) wg_count = 0;
     unsigned long long local = 0;
+    const bool vec = S == 1 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    const uint32_t n_chunks = deg / kChunk + 1;
     const uint64_t tiles = tiles_per_phase * S;
+    Stage<KIND> st;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const uint32_t p = (uint32_t)(tile / tiles_per_phase);
         const uint64_t k0 = (tile % tiles_per_phase) * kTile;
@@ -130,41 +200,64 @@ __global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict_
         const uint64_t valid = nk > deg ? nk - deg : 0;          // offsets k < valid are checked
         if (k0 >= valid) continue;                               // the same for the whole workgroup
         uint32_t acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (uint32_t i0 = 0; i0 <= deg; i0 += kChunk) {
+        st.fetch(src, vec, p, S, k0, nk, t);
+        for (uint32_t c = 0; c < n_chunks; c++) {
+            const uint32_t i0 = c * kChunk;
             __syncthreads();  // the previous chunk's reads are done
-            for (uint32_t j = t; j < (uint32_t)kBuf; j += kThreads) {
-                const uint64_t k = k0 + i0 + j;
-                buf[lds_slot(j)] = k < nk ? stream_word<KIND>(src, p + k * S) : 0u;
-            }
+            st.template store<DENSE>(buf, t);
             __syncthreads();
-            const uint32_t* Ac = A + i0 / 32;
-            for (int q = 0; q < kChunk / 32; q++) {
-                const uint32_t a = uniform(Ac[q]);
-                if (a == 0) continue;
-                // window: buffer words 32 q + kR t + 0 .. kWin - 1 = 8-word groups
-                // 4 q + t .. 4 q + t + 4; the last word is
-                // 32 (kChunk/32 - 1) + kR (kThreads - 1) + kWin - 1 = kBuf - 1
-                const uint4* lo = reinterpret_cast<const uint4*>(buf) + 4 * q + t;
-                const uint4* hi = reinterpret_cast<const uint4*>(buf + kBuf / 2) + 4 * q + t;
-                uint32_t w[kWin];
+            if (c + 1 < n_chunks) st.fetch(src, vec, p, S, k0 + i0 + kChunk, nk, t);  // in flight meanwhile
+            if constexpr (DENSE) {
+                const uint32_t* Ac = A + i0 / 32;
+                uint32_t a = uniform(Ac[0]);
+                for (int q = 0; q < kChunk / 32; q++) {
+                    const uint32_t a_next = q + 1 < kChunk / 32 ? uniform(Ac[q + 1]) : 0u;
+                    if (a != 0) {
+                        // window: buffer words 32 q + kR t + 0 .. kWin - 1 = 8-word groups
+                        // 4 q + t .. 4 q + t + 4; the last word is
+                        // 32 (kChunk/32 - 1) + kR (kThreads - 1) + kWin - 1 = kBuf - 1
+                        const uint4* lo = reinterpret_cast<const uint4*>(buf) + 4 * q + t;
+                        const uint4* hi = reinterpret_cast<const uint4*>(buf + kBuf / 2) + 4 * q + t;
+                        uint32_t w[kWin];
 #pragma unroll
-                for (int m = 0; m < kWin / 8; m++) {
-                    const uint4 u = lo[m], v = hi[m];
-                    w[8 * m] = u.x;
-                    w[8 * m + 1] = u.y;
-                    w[8 * m + 2] = u.z;
-                    w[8 * m + 3] = u.w;
-                    w[8 * m + 4] = v.x;
-                    w[8 * m + 5] = v.y;
-                    w[8 * m + 6] = v.z;
-                    w[8 * m + 7] = v.w;
+                        for (int m = 0; m < kWin / 8; m++) {
+                            const uint4 u = lo[m], v = hi[m];
+                            w[8 * m] = u.x;
+                            w[8 * m + 1] = u.y;
+                            w[8 * m + 2] = u.z;
+                            w[8 * m + 3] = u.w;
+                            w[8 * m + 4] = v.x;
+                            w[8 * m + 5] = v.y;
+                            w[8 * m + 6] = v.z;
+                            w[8 * m + 7] = v.w;
+                        }
+#pragma unroll
+                        for (int n = 0; n < 8; n++) apply_nibble((a >> (4 * n)) & 15u, acc, w + 4 * n);
+                    }
+                    a = a_next;
                 }
+            } else {
+                // coefficient offset d < kChunk, offset t + kThreads r < kTile: index < kBuf
+                const uint32_t e_end = uniform(Eoff[c + 1]);
+                uint32_t e = uniform(Eoff[c]);
+                for (; e + 1 < e_end; e += 2) {
+                    const uint32_t* b1 = buf + (uniform(E[e]) - i0) + t;
+                    const uint32_t* b2 = buf + (uniform(E[e + 1]) - i0) + t;
 #pragma unroll
-                for (int n = 0; n < 8; n++) apply_nibble((a >> (4 * n)) & 15u, acc, w + 4 * n);
+                    for (int r = 0; r < kR; r++) acc[r] = xor3(acc[r], b1[kThreads * r], b2[kThreads * r]);
+                }
+                if (e < e_end) {
+                    const uint32_t* b1 = buf + (uniform(E[e]) - i0) + t;
+#pragma unroll
+                    for (int r = 0; r < kR; r++) acc[r] ^= b1[kThreads * r];
+                }
             }
         }
 #pragma unroll
-        for (int r = 0; r < kR; r++) local += (k0 + kR * t + r < valid && acc[r] != 0) ? 1u : 0u;
+        for (int r = 0; r < kR; r++) {
+            const uint64_t k = k0 + (DENSE ? kR * t + r : t + kThreads * r);
+            local += (k < valid && acc[r] != 0) ? 1u : 0u;
+        }
     }
     __syncthreads();
     if (local) atomicAdd(&wg_count, local);
@@ -172,30 +265,33 @@ __global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict_
     if (t == 0 && wg_count) atomicAdd(count, wg_count);
 }
 
+template <int KIND>
+void launch_kind(const CheckPolyDev& poly, uint32_t grid, hipStream_t stream, const void* src, uint64_t nw,
+                 uint32_t S, uint64_t tpp, unsigned long long* count) {
+    if (poly.dense)
+        check_kernel<KIND, true><<<grid, kThreads, 0, stream>>>(src, nw, S, poly.bits, poly.terms, poly.term_off,
+                                                               poly.deg, tpp, count);
+    else
+        check_kernel<KIND, false><<<grid, kThreads, 0, stream>>>(src, nw, S, poly.bits, poly.terms, poly.term_off,
+                                                                poly.deg, tpp, count);
+}
+
 }  // namespace
 
-hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const uint32_t* d_A, uint32_t deg,
+hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const CheckPolyDev& poly,
                         unsigned long long* d_count, uint32_t max_grid, hipStream_t stream) {
     zero_count_kernel<<<1, 1, 0, stream>>>(d_count);
     const uint64_t nk0 = (nw + S - 1) / S;  // phase 0 is the longest
-    const uint64_t valid0 = nk0 > deg ? nk0 - deg : 0;
+    const uint64_t valid0 = nk0 > poly.deg ? nk0 - poly.deg : 0;
     const uint64_t tiles_per_phase = (valid0 + kTile - 1) / kTile;
     const uint64_t tiles = tiles_per_phase * S;
     if (tiles == 0) return hipGetLastError();
     const uint32_t grid = (uint32_t)(tiles < max_grid ? tiles : max_grid);
     switch (out_kind) {
-        case kOutU32:
-            check_kernel<kOutU32><<<grid, kThreads, 0, stream>>>(src, nw, S, d_A, deg, tiles_per_phase, d_count);
-            break;
-        case kOutF32:
-            check_kernel<kOutF32><<<grid, kThreads, 0, stream>>>(src, nw, S, d_A, deg, tiles_per_phase, d_count);
-            break;
-        case kOutU64:
-            check_kernel<kOutU64><<<grid, kThreads, 0, stream>>>(src, nw, S, d_A, deg, tiles_per_phase, d_count);
-            break;
-        default:
-            check_kernel<kOutF64><<<grid, kThreads, 0, stream>>>(src, nw, S, d_A, deg, tiles_per_phase, d_count);
-            break;
+        case kOutU32: launch_kind<kOutU32>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
+        case kOutF32: launch_kind<kOutF32>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
+        case kOutU64: launch_kind<kOutU64>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
+        default: launch_kind<kOutF64>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
     }
     return hipGetLastError();
 }

@@ -49,11 +49,17 @@ struct BatchShape {
 
 // Linear-complexity self-check: count the offsets x < nw - deg S of the
 // stream's 32-bit words w (out_kind gives the element type) where the XOR of
-// w[x + i S] over the set coefficients i of A is nonzero. d_A: deg + 1
-// coefficients as uint32 words, zero-padded to a multiple of kCheckChunkBits
-// bits. *d_count is overwritten (a fill kernel, not a memset).
+// w[x + i S] over the set coefficients i of A is nonzero. *d_count is
+// overwritten (a fill kernel, not a memset).
 constexpr uint32_t kCheckChunkBits = 4096;
-hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const uint32_t* d_A, uint32_t deg,
+struct CheckPolyDev {
+    uint32_t deg = 0;
+    bool dense = false;                // dense form (bit pattern) or sparse form (coefficient list)
+    const uint32_t* bits = nullptr;    // deg + 1 bits as uint32 words, zero-padded to kCheckChunkBits
+    const uint32_t* terms = nullptr;   // set coefficients, increasing
+    const uint32_t* term_off = nullptr;  // deg / kCheckChunkBits + 2 entries: terms of chunk c start at term_off[c]
+};
+hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const CheckPolyDev& poly,
                         unsigned long long* d_count, uint32_t max_grid, hipStream_t stream);
 
 // Persistent batched generation. d_counter points to two uint32 that must be
