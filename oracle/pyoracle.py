@@ -21,10 +21,19 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 OR_PW = 640
 
 MT32, MT64, SFMT = 0, 1, 2
-STATE_WORDS = {MT32: 624, MT64: 312, SFMT: 156}
-STATE_DTYPE = {MT32: np.uint32, MT64: np.uint64, SFMT: np.uint32}
-STATE_LEN = {MT32: 624, MT64: 312, SFMT: 624}  # numpy elements per state
-OUT_DTYPE = {MT32: np.uint32, MT64: np.uint64, SFMT: np.uint32}
+# SFMT with the other published parameter sets (same recurrence, Mersenne exponent in the name)
+SFMT607, SFMT1279, SFMT2281, SFMT4253, SFMT11213 = 3, 4, 5, 6, 7
+SFMT_FAMILY = (SFMT, SFMT607, SFMT1279, SFMT2281, SFMT4253, SFMT11213)
+MEXP = {MT32: 19937, MT64: 19937, SFMT: 19937, SFMT607: 607, SFMT1279: 1279, SFMT2281: 2281, SFMT4253: 4253,
+        SFMT11213: 11213}
+STATE_WORDS = {MT32: 624, MT64: 312, **{v: MEXP[v] // 128 + 1 for v in SFMT_FAMILY}}
+STATE_DTYPE = {MT32: np.uint32, MT64: np.uint64, **{v: np.uint32 for v in SFMT_FAMILY}}
+STATE_LEN = {MT32: 624, MT64: 312, **{v: 4 * STATE_WORDS[v] for v in SFMT_FAMILY}}  # numpy elements per state
+OUT_DTYPE = {MT32: np.uint32, MT64: np.uint64, **{v: np.uint32 for v in SFMT_FAMILY}}
+
+
+def is_sfmt(variant: int) -> bool:
+    return variant in SFMT_FAMILY
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +66,11 @@ def lib():
         L.or_mt64_init_genrand.argtypes = [P, ctypes.c_uint64]
         L.or_sfmt_init_genrand.argtypes = [P, ctypes.c_uint32]
         L.or_sfmt_init_genrand.restype = ctypes.c_int
+        L.or_sfmt_init.argtypes = [ctypes.c_int, P, ctypes.c_uint32]
+        L.or_sfmt_init.restype = ctypes.c_int
+        L.or_sfmt_parity.argtypes = [ctypes.c_int, P]
+        L.or_mexp.argtypes = [ctypes.c_int]
+        L.or_mexp.restype = ctypes.c_int
         L.or_mt32_temper.argtypes = [ctypes.c_uint32]
         L.or_mt32_temper.restype = ctypes.c_uint32
         L.or_mt64_temper.argtypes = [ctypes.c_uint64]
@@ -72,6 +86,8 @@ def lib():
         L.or_poly_gcd.argtypes = [P, P, P]
         L.or_berlekamp_massey.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t]
         L.or_berlekamp_massey.restype = ctypes.c_int
+        L.or_minpoly_masked.argtypes = [ctypes.c_int, P, P, P]
+        L.or_minpoly_masked.restype = ctypes.c_int
         L.or_minpoly.argtypes = [ctypes.c_int, P, P]
         L.or_minpoly.restype = ctypes.c_int
         L.or_jump.argtypes = [ctypes.c_int, P, P]
@@ -170,6 +186,16 @@ def minpoly(variant: int, canon: np.ndarray) -> int:
     return words_to_poly(mu)
 
 
+def minpoly_masked(variant: int, canon: np.ndarray, mask: np.ndarray) -> int:
+    """Minimal polynomial of the sequence <mask, X_i> (mask: the state's layout as uint32)."""
+    mu = np.zeros(OR_PW, np.uint64)
+    c = np.ascontiguousarray(canon, dtype=STATE_DTYPE[variant])
+    m = np.ascontiguousarray(mask, dtype=np.uint32)
+    assert m.nbytes == c.nbytes
+    lib().or_minpoly_masked(variant, _ptr(c), _ptr(m), _ptr(mu))
+    return words_to_poly(mu)
+
+
 # ---- seeding ----------------------------------------------------------------
 
 
@@ -186,13 +212,19 @@ def seed_state(variant: int, seed: int | None = None, key=None) -> np.ndarray:
     elif variant == MT64:
         lib().or_mt64_init_genrand(_ptr(x), seed)
     else:
-        lib().or_sfmt_init_genrand(_ptr(x), seed)
+        lib().or_sfmt_init(variant, _ptr(x), seed)
     return x
 
 
-def sfmt_certification_flipped(seed: int) -> bool:
-    x = np.zeros(624, np.uint32)
-    return bool(lib().or_sfmt_init_genrand(_ptr(x), seed))
+def sfmt_certification_flipped(seed: int, variant: int = SFMT) -> bool:
+    x = np.zeros(STATE_LEN[variant], np.uint32)
+    return bool(lib().or_sfmt_init(variant, _ptr(x), seed))
+
+
+def sfmt_parity(variant: int) -> np.ndarray:
+    p = np.zeros(4, np.uint32)
+    lib().or_sfmt_parity(variant, _ptr(p))
+    return p
 
 
 # ---- scalar generators ----------------------------------------------------
@@ -207,7 +239,7 @@ class Scalar:
         self.k = ctypes.c_int(0)
 
     def _run(self, count: int, temper: int) -> np.ndarray:
-        shape = (count, 4) if self.variant == SFMT else (count,)
+        shape = (count, 4) if is_sfmt(self.variant) else (count,)
         out = np.zeros(shape, OUT_DTYPE[self.variant])
         lib().or_step(self.variant, _ptr(self.buf), ctypes.byref(self.k), _ptr(out), count, temper)
         return out

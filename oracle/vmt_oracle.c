@@ -47,20 +47,44 @@
 #define MT64_L 0x000000007FFFFFFFull
 #define MT64_A 0xB5026F5AA96619E9ull
 
-/* SFMT19937: N = 156 128-bit words, m = 122, mask K. */
-#define SFMT_N 156
-#define SFMT_M 122
-static const uint32_t SFMT_K[4] = {0xDFFFFFEFu, 0xDDFECB7Fu, 0xBFFAFFFFu, 0xBFFFFFF6u};
-/* Period-certification parity vector of the published SFMT19937 parameter
- * set (not in the paper; checked algebraically by the tests). */
-static const uint32_t SFMT_PARITY[4] = {0x00000001u, 0x00000000u, 0x00000000u, 0x13c9e684u};
+/* SFMT, eq. (sfmt_step) and eq. (sfmt_params) for SFMT19937: N = MEXP/128 + 1
+ * 128-bit words, pick-up position m (POS1), 128-bit shifts by SL2 and SR2
+ * bytes, 32-bit sub-word shifts SL1 and SR1, mask K (MSK). The paper gives
+ * the SFMT19937 set; the other Mersenne exponents are the generator authors'
+ * published sets (Saito-Matsumoto), through the same recurrence. PARITY is
+ * the period-certification vector of each set (not in the paper; the tests
+ * check every set algebraically: the minimal polynomial has an irreducible
+ * factor of degree MEXP, and PARITY annihilates the rest). */
+typedef struct {
+    int mexp, n, m, sl1, sl2, sr1, sr2;
+    uint32_t k[4], parity[4];
+} sfmt_params;
+
+static const sfmt_params SFMT_SETS[6] = {
+    {19937, 156, 122, 18, 1, 11, 1, {0xdfffffefu, 0xddfecb7fu, 0xbffaffffu, 0xbffffff6u},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x13c9e684u}},
+    {607, 5, 2, 15, 3, 13, 3, {0xfdff37ffu, 0xef7f3f7du, 0xff777b7du, 0x7ff7fb2fu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x5986f054u}},
+    {1279, 10, 7, 14, 3, 5, 1, {0xf7fefffdu, 0x7fefcfffu, 0xaff3ef3fu, 0xb5ffff7fu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x20000000u}},
+    {2281, 18, 12, 19, 1, 5, 1, {0xbff7ffbfu, 0xfdfffffeu, 0xf7ffef7fu, 0xf2f7cbbfu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x41dfa600u}},
+    {4253, 34, 17, 20, 1, 7, 1, {0x9f7bffffu, 0x9fffff5fu, 0x3efffffbu, 0xfffff7bbu},
+     {0xa8000001u, 0xaf5390a3u, 0xb740b3f8u, 0x6c11486du}},
+    {11213, 88, 68, 14, 3, 7, 3, {0xeffff7fbu, 0xffffffefu, 0xdfdfbfffu, 0x7fffdbfdu},
+     {0x00000001u, 0x00000000u, 0xe8148000u, 0xd0c7afa3u}},
+};
+
+/* variant 2 = SFMT19937, 3..7 = SFMT607, 1279, 2281, 4253, 11213 */
+static const sfmt_params* sfmt_set(int variant) { return &SFMT_SETS[variant - 2]; }
 
 int or_state_words(int variant) {
-    return variant == 0 ? MT32_N : variant == 1 ? MT64_N : SFMT_N;
+    return variant == 0 ? MT32_N : variant == 1 ? MT64_N : sfmt_set(variant)->n;
 }
 int or_word_bytes(int variant) {
     return variant == 0 ? 4 : variant == 1 ? 8 : 16;
 }
+int or_mexp(int variant) { return variant < 2 ? 19937 : sfmt_set(variant)->mexp; }
 
 /* ------------------------------------------------------------------------ */
 /* Seeding. The paper starts from "a certain initial state" and gives no      */
@@ -109,21 +133,22 @@ void or_mt64_init_genrand(uint64_t x[312], uint64_t seed) {
         x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + i;
 }
 
-/* SFMT: MT32's init_genrand over the 624 32-bit sub-words (sub-word j of
+/* SFMT: MT32's init_genrand over the 4N 32-bit sub-words (sub-word j of
  * word k is index 4k + j), then period certification: if the parity of
  * <PARITY, word 0> is even, flip the lowest set bit of PARITY in word 0. */
-int or_sfmt_init_genrand(uint32_t x[624], uint32_t seed) {
+int or_sfmt_init(int variant, uint32_t* x, uint32_t seed) {
+    const sfmt_params* P = sfmt_set(variant);
     x[0] = seed;
-    for (uint32_t i = 1; i < 4 * SFMT_N; i++)
+    for (uint32_t i = 1; i < 4 * (uint32_t)P->n; i++)
         x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
     uint32_t inner = 0;
-    for (int j = 0; j < 4; j++) inner ^= x[j] & SFMT_PARITY[j];
+    for (int j = 0; j < 4; j++) inner ^= x[j] & P->parity[j];
     int parity = 0;
     for (int b = 0; b < 32; b++) parity ^= (int)((inner >> b) & 1u);
     if (parity == 1) return 0;
     for (int j = 0; j < 4; j++) {
         for (int b = 0; b < 32; b++) {
-            if ((SFMT_PARITY[j] >> b) & 1u) {
+            if ((P->parity[j] >> b) & 1u) {
                 x[j] ^= 1u << b;
                 return 1;
             }
@@ -131,6 +156,10 @@ int or_sfmt_init_genrand(uint32_t x[624], uint32_t seed) {
     }
     return 0;
 }
+
+int or_sfmt_init_genrand(uint32_t x[624], uint32_t seed) { return or_sfmt_init(2, x, seed); }
+
+void or_sfmt_parity(int variant, uint32_t parity[4]) { memcpy(parity, sfmt_set(variant)->parity, 16); }
 
 /* ------------------------------------------------------------------------ */
 /* Tempering, eq. (tempering); the first line tempers the new word itself.   */
@@ -187,27 +216,30 @@ static void u128_store(uint32_t w[4], uint64_t lo, uint64_t hi) {
     w[3] = (uint32_t)(hi >> 32);
 }
 
-/* eq. (sfmt_step):
- *   w_{k+N} = w_k ^ (w_k <<< 8) ^ ((w_{k+m} >> 11) & K) ^ (w_{k+N-2} >>> 8)
- *             ^ (w_{k+N-1} << 18)
+/* eq. (sfmt_step), with the set's parameters (SFMT19937: m = 122, SL2 = SR2 =
+ * 1 byte, SR1 = 11, SL1 = 18):
+ *   w_{k+N} = w_k ^ (w_k <<< 8 SL2) ^ ((w_{k+m} >> SR1) & K) ^ (w_{k+N-2} >>> 8 SR2)
+ *             ^ (w_{k+N-1} << SL1)
  * <<< / >>> shift the whole 128-bit word, << / >> each 32-bit sub-word. */
-static void sfmt_step(uint32_t* x, int* k, uint32_t out[4]) {
-    int i = *k;
+static void sfmt_step(int variant, uint32_t* x, int* k, uint32_t out[4]) {
+    const sfmt_params* P = sfmt_set(variant);
+    const int N = P->n, i = *k;
+    const int sl = 8 * P->sl2, sr = 8 * P->sr2; /* 8 .. 24 bits */
     const uint32_t* a = x + 4 * i;
-    const uint32_t* b = x + 4 * ((i + SFMT_M) % SFMT_N);
-    const uint32_t* c = x + 4 * ((i + SFMT_N - 2) % SFMT_N);
-    const uint32_t* d = x + 4 * ((i + SFMT_N - 1) % SFMT_N);
+    const uint32_t* b = x + 4 * ((i + P->m) % N);
+    const uint32_t* c = x + 4 * ((i + N - 2) % N);
+    const uint32_t* d = x + 4 * ((i + N - 1) % N);
     uint64_t lo, hi;
     uint32_t a_shl[4], c_shr[4], r[4];
     u128_load(a, &lo, &hi);
-    u128_store(a_shl, lo << 8, (hi << 8) | (lo >> 56));
+    u128_store(a_shl, lo << sl, (hi << sl) | (lo >> (64 - sl)));
     u128_load(c, &lo, &hi);
-    u128_store(c_shr, (lo >> 8) | (hi << 56), hi >> 8);
+    u128_store(c_shr, (lo >> sr) | (hi << (64 - sr)), hi >> sr);
     for (int j = 0; j < 4; j++)
-        r[j] = a[j] ^ a_shl[j] ^ ((b[j] >> 11) & SFMT_K[j]) ^ c_shr[j] ^ (d[j] << 18);
+        r[j] = a[j] ^ a_shl[j] ^ ((b[j] >> P->sr1) & P->k[j]) ^ c_shr[j] ^ (d[j] << P->sl1);
     memcpy(x + 4 * i, r, sizeof r);
     if (out) memcpy(out, r, sizeof r);
-    *k = (i + 1) % SFMT_N;
+    *k = (i + 1) % N;
 }
 
 void or_step(int variant, void* buf, int* k, void* out, size_t count, int temper) {
@@ -219,7 +251,7 @@ void or_step(int variant, void* buf, int* k, void* out, size_t count, int temper
             uint64_t v = mt64_step((uint64_t*)buf, k);
             if (out) ((uint64_t*)out)[s] = temper ? or_mt64_temper(v) : v;
         } else {
-            sfmt_step((uint32_t*)buf, k, out ? (uint32_t*)out + 4 * s : NULL);
+            sfmt_step(variant, (uint32_t*)buf, k, out ? (uint32_t*)out + 4 * s : NULL);
         }
     }
 }
@@ -402,7 +434,7 @@ int or_berlekamp_massey(const uint8_t* s, size_t N, uint64_t* poly, size_t poly_
 }
 
 int or_minpoly(int variant, const void* canon, uint64_t* mu) {
-    const int maxdeg = 19968;                  /* nw bits: upper bound on deg mu */
+    const int maxdeg = variant < 2 ? 19968 : 128 * or_state_words(variant); /* >= deg mu */
     const int N = 2 * maxdeg + 64;             /* terms of the sequence */
     int n = or_state_words(variant), wb = or_word_bytes(variant);
     unsigned char* buf = (unsigned char*)malloc((size_t)n * wb);
@@ -420,11 +452,53 @@ int or_minpoly(int variant, const void* canon, uint64_t* mu) {
             or_step(1, buf, &k, &v, 1, 0);
             s[i] = (uint8_t)(v & 1u);
         } else {
-            or_step(2, buf, &k, w4, 1, 0);
+            or_step(variant, buf, &k, w4, 1, 0);
             s[i] = (uint8_t)(w4[0] & 1u);
         }
     }
     int L = or_berlekamp_massey(s, (size_t)N, mu, OR_PW);
+    free(buf);
+    free(s);
+    return L;
+}
+
+/* Minimal polynomial of the sequence s_i = <mask, X_i> (parity of the AND of
+ * a bit mask with the canonical state after i steps), N = 2 * dim + 64 terms.
+ * One output bit need not observe every part of the state; a random mask
+ * does with high probability, and the lcm over a few such sequences is the
+ * minimal polynomial of the map itself. mask has the canonical state's layout
+ * (n words of the variant's width, as uint32). */
+int or_minpoly_masked(int variant, const void* canon, const uint32_t* mask, uint64_t* mu) {
+    const int n = or_state_words(variant), wb = or_word_bytes(variant);
+    const int u32_per_word = wb / 4;
+    const int dim = variant < 2 ? 19968 : 128 * n;
+    const int N = 2 * dim + 64;
+    const size_t words = (size_t)n + (size_t)N; /* raw words x_0 .. x_{n+N-1} */
+    uint32_t* raw = (uint32_t*)malloc(words * wb);
+    unsigned char* buf = (unsigned char*)malloc((size_t)n * wb);
+    memcpy(buf, canon, (size_t)n * wb);
+    memcpy(raw, canon, (size_t)n * wb);
+    int k = 0;
+    for (int i = 0; i < N; i++) {
+        unsigned char* dst = (unsigned char*)raw + ((size_t)n + i) * wb;
+        if (variant == 0) {
+            or_step(0, buf, &k, dst, 1, 0);
+        } else if (variant == 1) {
+            or_step(1, buf, &k, dst, 1, 0);
+        } else {
+            or_step(variant, buf, &k, dst, 1, 0);
+        }
+    }
+    uint8_t* s = (uint8_t*)malloc(N);
+    const int mw = n * u32_per_word;
+    for (int i = 0; i < N; i++) {
+        const uint32_t* win = raw + (size_t)i * u32_per_word;
+        uint32_t acc = 0;
+        for (int j = 0; j < mw; j++) acc ^= win[j] & mask[j];
+        s[i] = (uint8_t)__builtin_parity(acc);
+    }
+    int L = or_berlekamp_massey(s, (size_t)N, mu, OR_PW);
+    free(raw);
     free(buf);
     free(s);
     return L;
@@ -507,7 +581,7 @@ void or_vgen_generate(or_vgen* v, void* out, size_t count) {
             uint64_t e = v->pos / 4;
             int j = (int)(v->pos % 4);
             int t = (int)(e % (uint64_t)v->M);
-            if (j == 0) or_step(2, v->buf + bytes * t, &v->k[t], v->cur + 4 * t, 1, 0);
+            if (j == 0) or_step(v->variant, v->buf + bytes * t, &v->k[t], v->cur + 4 * t, 1, 0);
             ((uint32_t*)out)[i] = v->cur[4 * t + j];
         }
         v->pos++;
@@ -523,7 +597,7 @@ void or_vgen_jump(or_vgen* v, const uint64_t* g) {
         memcpy(v->buf + bytes * t, canon, bytes);
         v->k[t] = 0;
         /* the newest word of the jumped lane is its pending 128-bit word */
-        if (v->variant == 2) memcpy(v->cur + 4 * t, canon + bytes - 16, 16);
+        if (v->variant >= 2) memcpy(v->cur + 4 * t, canon + bytes - 16, 16);
     }
     free(canon);
 }

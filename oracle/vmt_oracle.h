@@ -21,7 +21,9 @@
  * for the jump, and lanes advanced one after the other.
  *
  * Conventions
- *   variant 0 = MT19937-32, 1 = MT19937-64, 2 = SFMT19937.
+ *   variant 0 = MT19937-32, 1 = MT19937-64, 2 = SFMT19937, 3..7 = SFMT607,
+ *   SFMT1279, SFMT2281, SFMT4253, SFMT11213 (the same recurrence with the
+ *   generator authors' parameter sets for those Mersenne exponents).
  *   A "canonical" state lists the n words oldest first: x_k, ..., x_{k+n-1}.
  *   SFMT words are 128-bit, stored as four uint32 sub-words, sub-word 0 the
  *   least significant (value = sum_j w^(j) 2^(32 j)).
@@ -45,17 +47,23 @@ extern "C" {
 
 /* ---- base generators (scalar, circular buffer) --------------------------- */
 
-/* Number of state words n and the byte size of one word for a variant. */
+/* Number of state words n, the byte size of one word, and the Mersenne
+ * exponent (the period is a multiple of 2^MEXP - 1) of a variant. */
 int or_state_words(int variant);
 int or_word_bytes(int variant);
+int or_mexp(int variant);
 
 /* Seeding. The paper does not give a seeding procedure; these follow the
  * published initialisations of the base generators (see vmt_oracle.c). */
 void or_mt32_init_genrand(uint32_t x[624], uint32_t seed);
 void or_mt32_init_by_array(uint32_t x[624], const uint32_t* key, int key_len);
 void or_mt64_init_genrand(uint64_t x[312], uint64_t seed);
-/* Returns 1 if period certification flipped a bit, 0 if not. */
+/* SFMT of any variant >= 2: x holds 4N uint32. Returns 1 if period
+ * certification flipped a bit, 0 if not. or_sfmt_init_genrand is SFMT19937. */
+int or_sfmt_init(int variant, uint32_t* x, uint32_t seed);
 int or_sfmt_init_genrand(uint32_t x[624], uint32_t seed);
+/* The period-certification vector of an SFMT variant. */
+void or_sfmt_parity(int variant, uint32_t parity[4]);
 
 /* Tempering g() of eq. (tempering). */
 uint32_t or_mt32_temper(uint32_t y);
@@ -93,6 +101,12 @@ int or_berlekamp_massey(const uint8_t* s, size_t N, uint64_t* poly, size_t poly_
  * word) produced from the canonical state, by Berlekamp-Massey over
  * 2*maxdeg+64 terms. Returns its degree. */
 int or_minpoly(int variant, const void* canon, uint64_t* mu);
+
+/* Minimal polynomial of the sequence <mask, X_i> of a state's successors X_i
+ * (mask: a bit mask with the canonical state's layout, as uint32). Returns its
+ * degree. The lcm over a few random masks and states is the minimal
+ * polynomial of the one-step map. */
+int or_minpoly_masked(int variant, const void* canon, const uint32_t* mask, uint64_t* mu);
 
 /* ---- jump ahead ------------------------------------------------------------ */
 

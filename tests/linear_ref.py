@@ -2,8 +2,9 @@
 (test infrastructure: plain Python integer arithmetic over GF(2)).
 
 MT19937-32/-64: every bit of the V-stream obeys mu, the base minimal
-polynomial. SFMT19937: mu = phi psi with phi = gcd(mu, t^(2^19937) - t); the
-bits of the sequence of 128-bit words obey phi(t) psi(t^M) = phi psi^M.
+polynomial. SFMT (any parameter set): mu = phi psi with phi = gcd(mu,
+t^(2^MEXP) - t); the bits of the sequence of 128-bit words obey
+phi(t) psi(t^M) = phi psi^M.
 """
 from oracle import pyoracle as O
 from tests import golden_io
@@ -29,10 +30,11 @@ def pmul(a: int, b: int) -> int:
     return r
 
 
-def sfmt_factors():
-    """phi = gcd(mu, t^(2^19937) - t) and psi = mu / phi from the fixtures."""
-    mu = golden_io.minpoly(O.SFMT)
-    frob = golden_io.tpow2(O.SFMT)[D]  # t^(2^19937) mod mu
+def sfmt_factors(variant: int = O.SFMT):
+    """phi = gcd(mu, t^(2^MEXP) - t) and psi = mu / phi from the fixtures (phi
+    collects the factors whose roots alpha satisfy alpha^(2^MEXP) = alpha)."""
+    mu = golden_io.minpoly(variant)
+    frob = golden_io.tpow2(variant)[O.MEXP[variant]]  # t^(2^MEXP) mod mu
     phi = O.poly_gcd(mu, frob ^ 2)
     psi, rem = pdivmod(mu, phi)
     assert rem == 0
@@ -40,9 +42,9 @@ def sfmt_factors():
 
 
 def check_poly(variant: int, M: int) -> int:
-    if variant != O.SFMT:
+    if not O.is_sfmt(variant):
         return golden_io.minpoly(variant)
-    mu, phi, psi = sfmt_factors()
+    mu, phi, psi = sfmt_factors(variant)
     psiM = psi
     for _ in range(M.bit_length() - 1):
         psiM = pmul(psiM, psiM)  # psi(t)^2 = psi(t^2) over GF(2)
