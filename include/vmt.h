@@ -60,6 +60,17 @@ extern "C" {
 #define VMT_MT32 0
 #define VMT_MT64 1
 #define VMT_SFMT 2
+/* SFMT with the generator authors' parameter sets for other Mersenne
+ * exponents: the recurrence of eq. (sfmt_step) with other shifts, masks and
+ * N = MEXP / 128 + 1 words of 128 bits; the paper's claim that the method
+ * carries over to any F2-linear generator (Sec. 3.1, Sec. 5). Everything
+ * below that holds for VMT_SFMT holds for these, with 19937 replaced by the
+ * exponent (period multiple of 2^MEXP - 1, lane distance J = 2^(MEXP - log2 M)). */
+#define VMT_SFMT607 3
+#define VMT_SFMT1279 4
+#define VMT_SFMT2281 5
+#define VMT_SFMT4253 6
+#define VMT_SFMT11213 7
 
 /* output kinds for vmt_batch_generate */
 #define VMT_OUT_U32 0
@@ -242,7 +253,7 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
  * Every output bit of an F2-linear generator, read along its stream, obeys a
  * fixed linear recurrence; its length is the sequence's linear complexity,
  * which the paper reports as the one statistical test every MT-based
- * generator fails (Sec. 4, LinearComp). For the V-stream the recurrence is
+ * generator fails (Sec. 4.1, LinearComp). For the V-stream the recurrence is
  * known in closed form, so a generated buffer can be checked against it on
  * the device at any size:
  *

@@ -3,6 +3,8 @@
 
 #include <immintrin.h>
 
+#include "vmt_common.hpp"
+
 #include <algorithm>
 #include <cstring>
 #include <stdexcept>
@@ -345,13 +347,13 @@ Words berlekamp_massey(const std::vector<uint8_t>& s) {
 
 // ---- raw bit sequences of the base generators (block regeneration form) ------
 
-static std::vector<uint8_t> raw_bits(int variant, size_t count) {
+static std::vector<uint8_t> raw_bits(int variant, size_t count, uint32_t seed) {
     std::vector<uint8_t> bits;
     bits.reserve(count);
     if (variant == 0) {
         const int n = 624, m = 397;
         uint32_t x[624];
-        x[0] = 20230928u;
+        x[0] = seed;
         for (int i = 1; i < n; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + uint32_t(i);
         while (bits.size() < count) {
             for (int k = 0; k < n; k++) {  // eq. (stepnomod): in place, indices mod n
@@ -363,7 +365,7 @@ static std::vector<uint8_t> raw_bits(int variant, size_t count) {
     } else if (variant == 1) {
         const int n = 312, m = 156;
         uint64_t x[312];
-        x[0] = 20230928u;
+        x[0] = seed;
         for (int i = 1; i < n; i++)
             x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + uint64_t(i);
         while (bits.size() < count) {
@@ -374,12 +376,14 @@ static std::vector<uint8_t> raw_bits(int variant, size_t count) {
             for (int k = 0; k < n && bits.size() < count; k++) bits.push_back(uint8_t(x[k] & 1u));
         }
     } else {
-        const int N = 156, m = 122;
-        static const uint32_t K[4] = {0xDFFFFFEFu, 0xDDFECB7Fu, 0xBFFAFFFFu, 0xBFFFFFF6u};
-        unsigned __int128 w[156];
-        uint32_t s32[624];
-        s32[0] = 20230928u;
-        for (int i = 1; i < 624; i++) s32[i] = 1812433253u * (s32[i - 1] ^ (s32[i - 1] >> 30)) + uint32_t(i);
+        // SFMT, eq. (sfmt_step), with the variant's parameter set
+        const SfmtSet& P = sfmt_set((uint32_t)variant);
+        const int N = (int)P.n, m = (int)P.pos1;
+        const int sl2 = 8 * (int)P.sl2, sr2 = 8 * (int)P.sr2;
+        std::vector<unsigned __int128> w(N);
+        std::vector<uint32_t> s32(4 * N);
+        s32[0] = seed;
+        for (int i = 1; i < 4 * N; i++) s32[i] = 1812433253u * (s32[i - 1] ^ (s32[i - 1] >> 30)) + uint32_t(i);
         for (int k = 0; k < N; k++)
             w[k] = (unsigned __int128)s32[4 * k] | ((unsigned __int128)s32[4 * k + 1] << 32) |
                    ((unsigned __int128)s32[4 * k + 2] << 64) | ((unsigned __int128)s32[4 * k + 3] << 96);
@@ -389,10 +393,10 @@ static std::vector<uint8_t> raw_bits(int variant, size_t count) {
                 const unsigned __int128 a = w[k], b = w[(k + m) % N], c = w[(k + N - 2) % N], d = w[(k + N - 1) % N];
                 unsigned __int128 bm = 0, dl = 0;
                 for (int j = 0; j < 4; j++) {
-                    bm |= (unsigned __int128)((sub(b, j) >> 11) & K[j]) << (32 * j);
-                    dl |= (unsigned __int128)(sub(d, j) << 18) << (32 * j);
+                    bm |= (unsigned __int128)((sub(b, j) >> P.sr1) & P.msk[j]) << (32 * j);
+                    dl |= (unsigned __int128)(sub(d, j) << P.sl1) << (32 * j);
                 }
-                w[k] = a ^ (a << 8) ^ bm ^ (c >> 8) ^ dl;
+                w[k] = a ^ (a << sl2) ^ bm ^ (c >> sr2) ^ dl;
             }
             for (int k = 0; k < N && bits.size() < count; k++) bits.push_back(uint8_t(uint32_t(w[k]) & 1u));
         }
@@ -400,10 +404,73 @@ static std::vector<uint8_t> raw_bits(int variant, size_t count) {
     return bits;
 }
 
+// Sequence <mask, X_i>, i < count, of an SFMT set's states X_i from a
+// pseudo-random full state X_0 (splitmix64 words from `seed`, which also
+// gives the mask): X_i is the window of the N words w_i .. w_{i+N-1}.
+static std::vector<uint8_t> masked_bits(int variant, size_t count, uint64_t seed) {
+    const SfmtSet& P = sfmt_set((uint32_t)variant);
+    const int N = (int)P.n, m = (int)P.pos1;
+    const int sl2 = 8 * (int)P.sl2, sr2 = 8 * (int)P.sr2;
+    auto next = [&seed]() {
+        uint64_t z = (seed += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto word = [&next]() { return (unsigned __int128)next() | ((unsigned __int128)next() << 64); };
+    std::vector<unsigned __int128> w(N + count), mask(N);
+    for (int k = 0; k < N; k++) w[k] = word();
+    for (int k = 0; k < N; k++) mask[k] = word();
+    auto sub = [](unsigned __int128 v, int j) { return uint32_t(v >> (32 * j)); };
+    for (size_t k = N; k < N + count; k++) {  // eq. (sfmt_step) on the growing sequence
+        const unsigned __int128 a = w[k - N], b = w[k - N + m], c = w[k - 2], d = w[k - 1];
+        unsigned __int128 bm = 0, dl = 0;
+        for (int j = 0; j < 4; j++) {
+            bm |= (unsigned __int128)((sub(b, j) >> P.sr1) & P.msk[j]) << (32 * j);
+            dl |= (unsigned __int128)(sub(d, j) << P.sl1) << (32 * j);
+        }
+        w[k] = a ^ (a << sl2) ^ bm ^ (c >> sr2) ^ dl;
+    }
+    std::vector<uint8_t> bits(count);
+    for (size_t i = 0; i < count; i++) {
+        uint64_t acc = 0;
+        for (int k = 0; k < N; k++) {
+            const unsigned __int128 v = w[i + k] & mask[k];
+            acc ^= (uint64_t)v ^ (uint64_t)(v >> 64);
+        }
+        bits[i] = uint8_t(__builtin_parityll(acc));
+    }
+    return bits;
+}
+
+// The minimal polynomial of the map is the lcm of those of the sequences it
+// drives; one output bit, or one state, may miss a factor (SFMT's mu is not
+// irreducible). MT19937-32/-64: mu is irreducible, bit 0 of one state gives
+// it. SFMT19937: bit 0 of the seeded state reaches the state dimension 19968,
+// so it is mu. The other SFMT sets: the lcm over random functionals
+// <mask, X_i> of random states until the degree reaches the dimension or 16
+// in a row add nothing (a factor is missed with probability at most 2^-16).
 Words generator_minpoly(int variant) {
-    const size_t terms = 2 * 19968 + 256;
-    Words mu = berlekamp_massey(raw_bits(variant, terms));
+    const bool sfmt = is_sfmt((uint32_t)variant);
+    const size_t dim = sfmt ? 128 * (size_t)sfmt_set((uint32_t)variant).n : 19968;
+    const size_t terms = 2 * dim + 256;
+    Words mu = variant <= (int)kSFMT ? berlekamp_massey(raw_bits(variant, terms, 20230928u))
+                                     : berlekamp_massey(masked_bits(variant, terms, 20230928u));
     poly_trim(mu);
+    int quiet = 0;
+    for (uint64_t s = 1; sfmt && (size_t)poly_degree(mu) < dim && quiet < 16; s++) {
+        Words m2 = berlekamp_massey(masked_bits(variant, terms, 20230928u + 7919u * s));
+        poly_trim(m2);
+        Words rem;
+        poly_div(mu, m2, &rem);
+        if (poly_degree(rem) < 0) {
+            quiet++;
+            continue;
+        }
+        mu = poly_mul(mu, poly_div(m2, poly_gcd(mu, m2)));
+        poly_trim(mu);
+        quiet = 0;
+    }
     return mu;
 }
 

@@ -45,7 +45,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 bool valid_M(uint32_t M) { return M >= 1 && M <= 64 && (M & (M - 1)) == 0; }
-bool valid_variant(int v) { return v == VMT_MT32 || v == VMT_MT64 || v == VMT_SFMT; }
+bool valid_variant(int v) { return v >= VMT_MT32 && v < (int)vmt::kVariants; }
 int log2u(uint32_t M) { return 31 - __builtin_clz(M); }
 
 struct StateInfo {
@@ -86,15 +86,15 @@ struct vmt_ctx {
     int device = -1;
     std::mutex mu;
     std::unordered_map<const void*, StateInfo> reg;
-    std::unique_ptr<vmt::PolyMod> ring[3];
-    std::map<uint64_t, Words> pow2[3];                 // k -> t^(2^k) mod mu
-    std::map<uint32_t, LaneTable> lanes[3];            // M -> lane polynomials on the device
-    std::map<std::vector<uint64_t>, DevPoly> jumps[3];  // distance -> jump polynomial on the device (bounded)
-    std::map<uint32_t, DevPoly> pow2_dev[3];            // k -> t^(2^k) on the device (k <= 65536, never evicted:
+    std::unique_ptr<vmt::PolyMod> ring[vmt::kVariants];
+    std::map<uint64_t, Words> pow2[vmt::kVariants];                 // k -> t^(2^k) mod mu
+    std::map<uint32_t, LaneTable> lanes[vmt::kVariants];            // M -> lane polynomials on the device
+    std::map<std::vector<uint64_t>, DevPoly> jumps[vmt::kVariants];  // distance -> jump polynomial on the device (bounded)
+    std::map<uint32_t, DevPoly> pow2_dev[vmt::kVariants];            // k -> t^(2^k) on the device (k <= 65536, never evicted:
                                                          // servers and batches hold these pointers)
     std::map<uint32_t, vmt_shape> shapes;  // shape_key -> launch shape set by the caller or the autotuner
-    std::map<uint32_t, SplitTable> split[3];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
-    std::map<uint32_t, CheckPoly> check[3];   // M -> recurrence polynomial of the V-stream's bits
+    std::map<uint32_t, SplitTable> split[vmt::kVariants];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
+    std::map<uint32_t, CheckPoly> check[vmt::kVariants];   // M -> recurrence polynomial of the V-stream's bits
     std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
 };
 
@@ -138,7 +138,7 @@ const Words& pow2(vmt_ctx* ctx, int variant, uint64_t k) {
     if (it != cache.end()) return it->second;
     vmt::PolyMod& R = ring(ctx, variant);
     constexpr uint64_t kD = 19937;
-    if (variant != VMT_SFMT && R.degree() == (int)kD) {
+    if (!vmt::is_sfmt(variant) && R.degree() == (int)kD) {
         const uint64_t e = k % kD;
         if (e != k) {
             Words v = pow2(ctx, variant, e);
@@ -197,8 +197,8 @@ CheckPoly& check_poly(vmt_ctx* ctx, int variant, uint32_t M) {
     if (it != ctx->check[variant].end()) return it->second;
     vmt::PolyMod& R = ring(ctx, variant);
     Words A = R.modulus();
-    if (variant == VMT_SFMT) {
-        Words f = pow2(ctx, variant, 19937);  // t^(2^19937) mod mu
+    if (vmt::is_sfmt(variant)) {
+        Words f = pow2(ctx, variant, vmt::mexp(variant));  // t^(2^MEXP) mod mu
         f[0] ^= 2;                            // - t
         const Words phi = vmt::poly_gcd(R.modulus(), f);
         Words rem;
@@ -225,7 +225,7 @@ int lane_table(vmt_ctx* ctx, int variant, uint32_t M, LaneTable** out) {
     host[0] = 1;  // lane 0: t^0
     uint32_t max_deg = 0;
     if (M > 1) {
-        const Words gJ = pow2(ctx, variant, 19937u - (uint32_t)log2u(M));
+        const Words gJ = pow2(ctx, variant, vmt::mexp(variant) - (uint32_t)log2u(M));
         Words g = gJ;
         for (uint32_t t = 1; t < M; t++) {
             if (t > 1) g = R.mul(g, gJ);
@@ -293,7 +293,7 @@ int lookup(vmt_ctx* ctx, const void* d_state, StateInfo* info) {
 }
 
 uint32_t shape_key(int family, int variant, uint32_t M, int out_kind) {
-    return (uint32_t)family | (uint32_t)variant << 1 | (uint32_t)out_kind << 3 | (uint32_t)log2u(M) << 6;
+    return (uint32_t)family | (uint32_t)variant << 1 | (uint32_t)out_kind << 4 | (uint32_t)log2u(M) << 6;
 }
 
 // Shape in force for (family, variant, M, out_kind): the stored one, else the
@@ -311,7 +311,7 @@ vmt_shape current_shape(vmt_ctx* ctx, int family, int variant, uint32_t M, int o
 // side by side, about twice the rate of one workgroup for all lanes);
 // smaller calls and SFMT19937 keep whole groups of up to 16 lanes.
 uint32_t auto_lpw(int variant, uint32_t M, uint64_t n, size_t eb) {
-    if (variant != VMT_SFMT && n * eb >= (256u << 10)) return 1;
+    if (!vmt::is_sfmt(variant) && n * eb >= (256u << 10)) return 1;
     return M < 16 ? M : 16;
 }
 
@@ -336,8 +336,8 @@ int ceil_log2(uint64_t x) { return x <= 1 ? 0 : 64 - __builtin_clzll(x - 1); }
 // log2 of the chunk length in lane steps, or -1 for a single launch.
 int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t eb, int out_kind) {
     if (sh.split_log2 == kNeverSplit) return -1;
-    const uint64_t epw = variant == VMT_SFMT ? 4 : 1;  // stream elements per word
-    if (variant != VMT_SFMT && !vmt::batch_supported(variant, M, out_kind)) return -1;
+    const uint64_t epw = vmt::is_sfmt(variant) ? 4 : 1;  // stream elements per word
+    if (!vmt::is_sfmt(variant) && !vmt::batch_supported(variant, M, out_kind)) return -1;
     const uint64_t steps = ceil_div(n, M * epw);
     int v;
     if (sh.split_log2) {
@@ -349,7 +349,7 @@ int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t 
         // SFMT19937 from M MiB (its serial chains run at about 0.25 GB/s per lane). MT chunks: at most 1024
         // lane jumps per call, at least 1 MiB each; SFMT chunks: 2^14 lane steps (its per-chunk rate is low,
         // so many chunks pay off).
-        if (variant == VMT_SFMT) {
+        if (vmt::is_sfmt(variant)) {
             if (n * eb < (uint64_t)M << 20) return -1;
             v = 14;
         } else {
@@ -404,7 +404,7 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
 int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64_t n, uint8_t* d_out, int out_kind,
                    int v, hipStream_t stream) {
     const uint32_t M = info.M;
-    const uint64_t epw = info.variant == VMT_SFMT ? 4 : 1;
+    const uint64_t epw = vmt::is_sfmt(info.variant) ? 4 : 1;
     const uint64_t E = (1ull << v) * M * epw;  // elements per chunk
     const uint64_t C = ceil_div(n, E);
     const size_t eb = out_elem_bytes(out_kind);
@@ -442,8 +442,8 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     if (e == hipSuccess) e = vmt::launch_replicate(d_state, buf, (uint32_t)sb, sbs, (uint32_t)(C - 1), stream);
     if (e == hipSuccess) e = vmt::launch_jump(info.variant, M, d_jt, jt[0], (uint32_t)(C - 1), stream);
     if (e == hipSuccess) {
-        if (info.variant == VMT_SFMT) {
-            e = vmt::launch_batch_sfmt(M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
+        if (vmt::is_sfmt(info.variant)) {
+            e = vmt::launch_batch_sfmt(info.variant, M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
         } else {
             vmt::BatchShape shape;
             vmt::ctx_batch_shape(ctx, info.variant, M, out_kind, &shape);
@@ -552,7 +552,7 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
     if (count > 0xFFFFFFFFull) return fail(VMT_EINVAL, "too many tasks");
     int st = check_batch(ctx, d_states, count, info);
     if (st) return st;
-    const bool ok = info->variant == VMT_SFMT
+    const bool ok = vmt::is_sfmt(info->variant)
                         ? vmt::generate_supported(info->variant, info->M, info->M < 16 ? info->M : 16, out_kind)
                         : vmt::batch_supported(info->variant, info->M, out_kind);
     if (!ok)
@@ -577,9 +577,9 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
 // queue to balance), in slices of at most 65535 tasks (a grid dimension).
 hipError_t launch_tasks(int variant, uint32_t M, int out_kind, const vmt::BatchShape& shape,
                         const vmt::BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream) {
-    if (variant != VMT_SFMT) return vmt::launch_batch(variant, M, out_kind, shape, d_tasks, count, d_counter, stream);
+    if (!vmt::is_sfmt(variant)) return vmt::launch_batch(variant, M, out_kind, shape, d_tasks, count, d_counter, stream);
     for (uint32_t i = 0; i < count; i += 65535) {
-        hipError_t e = vmt::launch_batch_sfmt(M, M < 16 ? M : 16, out_kind, d_tasks + i, std::min(65535u, count - i),
+        hipError_t e = vmt::launch_batch_sfmt(variant, M, M < 16 ? M : 16, out_kind, d_tasks + i, std::min(65535u, count - i),
                                               stream);
         if (e != hipSuccess) return e;
     }
@@ -683,7 +683,7 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
     if (ctx->device >= 0) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
-        for (int v = 0; v < 3; v++) {
+        for (int v = 0; v < (int)vmt::kVariants; v++) {
             for (auto& kv : ctx->lanes[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->pow2_dev[v]) (void)hipFree(kv.second.d);
@@ -864,7 +864,7 @@ int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens
     if (e == hipSuccess) e = vmt::reset_counters(d_counter, stream);
     if (e == hipSuccess) {
         vmt::BatchShape shape;
-        if (info.variant != VMT_SFMT) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
+        if (!vmt::is_sfmt(info.variant)) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
         e = launch_tasks(info.variant, info.M, out_kind, shape, d_tasks, (uint32_t)count, d_counter, stream);
     }
     (void)hipFreeAsync(d_buf, stream);
@@ -904,7 +904,7 @@ vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const
     plan->M = info.M;
     plan->out_kind = out_kind;
     plan->count = (uint32_t)count;
-    if (info.variant != VMT_SFMT) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &plan->shape);
+    if (!vmt::is_sfmt(info.variant)) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &plan->shape);
     plan->d_tasks = reinterpret_cast<vmt::BatchTask*>(d_buf);
     plan->d_counter = reinterpret_cast<uint32_t*>(d_buf + ((bytes + 255) / 256) * 256);
     if (status) *status = VMT_OK;
@@ -1036,7 +1036,7 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
     if (variant != VMT_MT64 && wide)
         return fail(VMT_EVARIANT, "variant %d produces no 64-bit output kind %d", variant, out_kind);
     const uint32_t wpe = wide ? 2 : 1;
-    const uint32_t S = variant == VMT_SFMT ? 4 : wpe;
+    const uint32_t S = vmt::is_sfmt(variant) ? 4 : wpe;
     if ((uintptr_t)d_out % (4 * wpe) || (uintptr_t)d_count % 8)
         return fail(VMT_EINVAL, "misaligned stream or count pointer");
     if (n > (UINT64_MAX >> 2)) return fail(VMT_EINVAL, "stream too long");

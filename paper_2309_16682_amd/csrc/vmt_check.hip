@@ -1,7 +1,7 @@
 // vmt_check.hip -- gfx950 kernels of the linear-complexity self-check.
 //
 // Every output bit of an F2-linear generator, read along its stream, obeys
-// the linear recurrence of a polynomial A (Sec. 4 reports the resulting
+// the linear recurrence of a polynomial A (Sec. 4.1 reports the resulting
 // LinearComp failures of every MT-based generator; Sec. 3.1 gives the
 // polynomial view of the state map). Thirty-two bits are checked at once:
 // for every offset x, XOR over the set coefficients i of A of the 32-bit

@@ -16,7 +16,43 @@
 
 namespace vmt {
 
-enum : uint32_t { kMT32 = 0, kMT64 = 1, kSFMT = 2 };
+// Variants: the paper's three base generators, then SFMT with the generator
+// authors' parameter sets for the Mersenne exponents 607 ... 11213 (the same
+// recurrence, eq. (sfmt_step), with other shifts, masks and state sizes).
+enum : uint32_t {
+    kMT32 = 0, kMT64 = 1, kSFMT = 2,
+    kSFMT607 = 3, kSFMT1279 = 4, kSFMT2281 = 5, kSFMT4253 = 6, kSFMT11213 = 7,
+    kVariants = 8
+};
+
+// An SFMT parameter set: N = mexp / 128 + 1 words of 128 bits, pick-up
+// position pos1 (the paper's m), 32-bit sub-word shifts sl1 and sr1, 128-bit
+// shifts by sl2 and sr2 bytes, mask msk (the paper's K), and the
+// period-certification vector. SFMT19937 is eq. (sfmt_params); the parity
+// vectors and the other sets are from the generator's authors (Saito and
+// Matsumoto), each checked by the tests: the minimal polynomial of the
+// one-step map has an irreducible factor of degree mexp, and the parity
+// vector annihilates the rest.
+struct SfmtSet {
+    uint32_t mexp, n, pos1, sl1, sl2, sr1, sr2;
+    uint32_t msk[4], parity[4];
+};
+constexpr SfmtSet kSfmtSets[6] = {
+    {19937, 156, 122, 18, 1, 11, 1, {0xdfffffefu, 0xddfecb7fu, 0xbffaffffu, 0xbffffff6u},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x13c9e684u}},
+    {607, 5, 2, 15, 3, 13, 3, {0xfdff37ffu, 0xef7f3f7du, 0xff777b7du, 0x7ff7fb2fu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x5986f054u}},
+    {1279, 10, 7, 14, 3, 5, 1, {0xf7fefffdu, 0x7fefcfffu, 0xaff3ef3fu, 0xb5ffff7fu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x20000000u}},
+    {2281, 18, 12, 19, 1, 5, 1, {0xbff7ffbfu, 0xfdfffffeu, 0xf7ffef7fu, 0xf2f7cbbfu},
+     {0x00000001u, 0x00000000u, 0x00000000u, 0x41dfa600u}},
+    {4253, 34, 17, 20, 1, 7, 1, {0x9f7bffffu, 0x9fffff5fu, 0x3efffffbu, 0xfffff7bbu},
+     {0xa8000001u, 0xaf5390a3u, 0xb740b3f8u, 0x6c11486du}},
+    {11213, 88, 68, 14, 3, 7, 3, {0xeffff7fbu, 0xffffffefu, 0xdfdfbfffu, 0x7fffdbfdu},
+     {0x00000001u, 0x00000000u, 0xe8148000u, 0xd0c7afa3u}},
+};
+constexpr bool is_sfmt(uint32_t variant) { return variant >= kSFMT && variant < kVariants; }
+constexpr const SfmtSet& sfmt_set(uint32_t variant) { return kSfmtSets[variant - kSFMT]; }
 constexpr uint32_t kMagic = 0x31544d56u;  // "VMT1"
 constexpr uint32_t kVersion = 1;
 constexpr uint32_t kHeaderBytes = 256;
@@ -36,9 +72,14 @@ struct StateHeader {
 };
 static_assert(sizeof(StateHeader) == kHeaderBytes, "header size");
 
-inline uint32_t words_per_lane(uint32_t variant) { return variant == kMT32 ? 624 : variant == kMT64 ? 312 : 156; }
+inline uint32_t words_per_lane(uint32_t variant) {
+    return variant == kMT32 ? 624 : variant == kMT64 ? 312 : sfmt_set(variant).n;
+}
 inline uint32_t word_bytes(uint32_t variant) { return variant == kMT32 ? 4 : variant == kMT64 ? 8 : 16; }
-inline uint32_t elems_per_word(uint32_t variant) { return variant == kSFMT ? 4 : 1; }
+inline uint32_t elems_per_word(uint32_t variant) { return is_sfmt(variant) ? 4 : 1; }
+// Mersenne exponent: the period is a multiple of 2^mexp - 1, and the lane
+// distance of M lanes is J = 2^(mexp - log2 M) (Sec. 3, Table jvalues).
+inline uint32_t mexp(uint32_t variant) { return is_sfmt(variant) ? sfmt_set(variant).mexp : 19937; }
 
 // One unit of batched work: a state, its output buffer and element count.
 // If `flag` is set (host-visible memory), the workgroup adds 1 to it with

@@ -36,6 +36,8 @@
 // a lane, one 32-bit sub-word each (sfmt_block_quad).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "vmt_common.hpp"
 #include "vmt_launch.hpp"
 
@@ -57,7 +59,25 @@ struct MT64P {
     static constexpr int N = 312, MM = 156, D = N - MM;  // D = 156
     static constexpr int V = 2;
 };
-constexpr int kSfmtN = 156, kSfmtM = 122;
+// SFMT parameter set of the state size N (each set has its own N).
+constexpr int sfmt_index(int N) {
+    for (int i = 0; i < 6; i++)
+        if ((int)kSfmtSets[i].n == N) return i;
+    return -1;
+}
+template <int N>
+struct SfmtP {
+    static constexpr int I = sfmt_index(N);
+    static_assert(I >= 0, "no SFMT parameter set with this state size");
+    static constexpr int MM = kSfmtSets[I].pos1;
+    static constexpr int SL1 = kSfmtSets[I].sl1, SL2 = 8 * kSfmtSets[I].sl2;  // bits
+    static constexpr int SR1 = kSfmtSets[I].sr1, SR2 = 8 * kSfmtSets[I].sr2;  // bits
+    static constexpr uint32_t K0 = kSfmtSets[I].msk[0], K1 = kSfmtSets[I].msk[1], K2 = kSfmtSets[I].msk[2],
+                              K3 = kSfmtSets[I].msk[3];
+    static constexpr uint32_t P0 = kSfmtSets[I].parity[0], P1 = kSfmtSets[I].parity[1],
+                              P2 = kSfmtSets[I].parity[2], P3 = kSfmtSets[I].parity[3];
+    static_assert(MM <= N - 2 && SL2 < 32 && SR2 < 32, "in-place chain and one-neighbour funnel shifts");
+};
 
 // a ^ (b & c) in one VALU op (v_bitop3_b32, truth table 0x78)
 __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
@@ -161,9 +181,11 @@ __device__ __forceinline__ uint64_t temper(uint64_t y) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// ---- SFMT19937, eq. (sfmt_step): 128-bit words as four 32-bit sub-words,
-// sub-word 0 least significant; w <<< 8 moves bits from sub-word j into
-// j + 1, w >>> 8 from j + 1 into j. Block regeneration by a quad of threads:
+// ---- SFMT, eq. (sfmt_step): 128-bit words as four 32-bit sub-words,
+// sub-word 0 least significant; w <<< 8 SL2 moves bits from sub-word j into
+// j + 1, w >>> 8 SR2 from j + 1 into j (SFMT19937: one byte each; every set
+// here shifts by at most three bytes, so only the neighbouring sub-word is
+// involved). Block regeneration by a quad of threads:
 // thread j of the quad owns sub-word j of every 128-bit word of one lane. The recurrence
 // is serial along the words (each new word reads the two before it), so the
 // quad splits each step four ways instead: the two shifts that cross
@@ -179,14 +201,15 @@ __device__ __forceinline__ uint32_t quad_prev(uint32_t x) {  // value of quad th
 }
 
 // src, dst: sub-word j of word k at [k * ws + j] (u32 units). src == dst runs
-// in place (word k is read before it is written; w_{k+m} for k + m >= N is a
-// new word written m - ... >= 2 steps earlier by this same thread).
+// in place (word k is read before it is written; w_{k+MM} for k + MM >= N is a
+// new word written N - MM >= 2 steps earlier by this same thread).
 // emit(k, value) is called for every new sub-word in order.
-template <class Emit>
+template <int N, class Emit>
 __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* dst, int ws, int j, Emit emit) {
-    constexpr int N = kSfmtN, MM = kSfmtM;
+    using P = SfmtP<N>;
+    constexpr int MM = P::MM;
     // the mask K of eq. (sfmt_params), sub-word j
-    const uint32_t K = j == 0 ? 0xDFFFFFEFu : j == 1 ? 0xDDFECB7Fu : j == 2 ? 0xBFFAFFFFu : 0xBFFFFFF6u;
+    const uint32_t K = j == 0 ? P::K0 : j == 1 ? P::K1 : j == 2 ? P::K2 : P::K3;
     const uint32_t lo_mask = j ? ~0u : 0u;  // sub-word 0 has no lower neighbour
     const uint32_t hi_mask = j < 3 ? ~0u : 0u;  // sub-word 3 has no upper neighbour
     // cn, dn: the upper neighbour's sub-word of c and d, zero for sub-word 3
@@ -200,12 +223,12 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
             a = src[(k + 1) * ws + j];
             b = k + 1 + MM < N ? src[(k + 1 + MM) * ws + j] : dst[(k + 1 + MM - N) * ws + j];
         }
-        // (a <<< 8) and (c >>> 8) on this sub-word: a funnel shift with the neighbour's sub-word
-        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak) & lo_mask, 24);
-        const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, 8);
+        // (a <<< SL2) and (c >>> SR2) on this sub-word: funnel shifts with the neighbour's sub-word
+        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak) & lo_mask, 32 - P::SL2);
+        const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, P::SR2);
         uint32_t r = xor3(ak, al, cr);
-        r = xor_and(r, bk >> 11, K);
-        r ^= d << 18;
+        r = xor_and(r, bk >> P::SR1, K);
+        r ^= d << P::SL1;
         dst[k * ws + j] = r;
         emit(k, r);
         c = d;
@@ -573,9 +596,8 @@ __global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) vo
 // lanes in parallel.
 // ---------------------------------------------------------------------------
 
-template <int LPW, int OUT>
+template <int N, int LPW, int OUT>
 struct SfmtGen {
-    static constexpr int N = kSfmtN, MM = kSfmtM;
     using OutT = typename OutOf<OUT == 0 ? 0 : 1, uint32_t>::T;
 
     static __device__ __forceinline__ OutT map(uint32_t v) {
@@ -637,11 +659,11 @@ struct SfmtGen {
                 const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
                 const uint32_t base = 4u * (lane0 + q) + j;  // output index of word 0's sub-word j
                 if (lim == B) {
-                    sfmt_block_quad(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
+                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
                         ob[base + 4u * M * k] = map(r);
                     });
                 } else {
-                    sfmt_block_quad(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
+                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
                         const uint32_t o = base + 4u * M * k;
                         if (o < lim) ob[o] = map(r);
                     });
@@ -660,20 +682,20 @@ struct SfmtGen {
     }
 };
 
-template <int LPW, int OUT>
+template <int N, int LPW, int OUT>
 __global__ __launch_bounds__(64) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len, int write_pos) {
-    using G = SfmtGen<LPW, OUT>;
-    __shared__ uint4 win[kSfmtN * LPW];
+    using G = SfmtGen<N, LPW, OUT>;
+    __shared__ uint4 win[N * LPW];
     G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
 }
 
 // Batched SFMT generation: workgroup (g, t) runs lane group g of task t.
 // With several groups per state the positions are fixed afterwards
 // (finalize_batch_pos), since every group reads the header first.
-template <int LPW, int OUT>
+template <int N, int LPW, int OUT>
 __global__ __launch_bounds__(64) void batch_sfmt_kernel(const BatchTask* tasks) {
-    using G = SfmtGen<LPW, OUT>;
-    __shared__ uint4 win[kSfmtN * LPW];
+    using G = SfmtGen<N, LPW, OUT>;
+    __shared__ uint4 win[N * LPW];
     const BatchTask task = tasks[blockIdx.y];
     G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
 }
@@ -748,10 +770,11 @@ __device__ void raw_twist_rows(const typename P::W* src, typename P::W* dst, int
 }
 
 
+template <int N>
 __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int stride, int tid) {
     const int row = tid >> 2, j = tid & 3;  // one quad of threads per row
     if (row >= rows) return;
-    sfmt_block_quad(reinterpret_cast<const uint32_t*>(src + row * stride), reinterpret_cast<uint32_t*>(dst + row * stride),
+    sfmt_block_quad<N>(reinterpret_cast<const uint32_t*>(src + row * stride), reinterpret_cast<uint32_t*>(dst + row * stride),
                     4, j, [](int, uint32_t) {});
 }
 
@@ -892,37 +915,36 @@ __device__ void seed_mt64(uint64_t* x, const InitTask& t) {
     x[0] = t.seed;
     for (uint64_t i = 1; i < 312; i++) x[i] = 6364136223846793005ull * (x[i - 1] ^ (x[i - 1] >> 62)) + i;
 }
+template <int N>
 __device__ void seed_sfmt(uint4* w, const InitTask& t) {
+    using P = SfmtP<N>;
     uint32_t* x = reinterpret_cast<uint32_t*>(w);
     x[0] = (uint32_t)t.seed;
-    for (uint32_t i = 1; i < 624; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
-    // period certification with the SFMT19937 parity vector (1, 0, 0, 0x13c9e684)
-    const uint32_t inner = (x[0] & 1u) ^ (x[3] & 0x13c9e684u);
-    if ((__builtin_popcount(inner) & 1) == 0) x[0] ^= 1u;
+    for (uint32_t i = 1; i < 4 * N; i++) x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
+    // period certification: if <PARITY, word 0> is even, flip the lowest set bit of PARITY
+    const uint32_t inner = (x[0] & P::P0) ^ (x[1] & P::P1) ^ (x[2] & P::P2) ^ (x[3] & P::P3);
+    if ((__builtin_popcount(inner) & 1) == 0) {
+        const uint32_t pv[4] = {P::P0, P::P1, P::P2, P::P3};
+        for (int j = 0; j < 4; j++)
+            if (pv[j]) {
+                x[j] ^= pv[j] & (0u - pv[j]);
+                break;
+            }
+    }
 }
-
-template <class W>
-__device__ void seed_state(W* x, const InitTask& t);
-template <>
-__device__ void seed_state<uint32_t>(uint32_t* x, const InitTask& t) { seed_mt32(x, t); }
-template <>
-__device__ void seed_state<uint64_t>(uint64_t* x, const InitTask& t) { seed_mt64(x, t); }
-template <>
-__device__ void seed_state<uint4>(uint4* x, const InitTask& t) { seed_sfmt(x, t); }
 
 template <class W, int N>
-__device__ void twist_rows(const W* src, W* dst, int rows, int stride, int tid, int nthr);
-template <>
-__device__ void twist_rows<uint32_t, 624>(const uint32_t* s, uint32_t* d, int rows, int stride, int tid, int nthr) {
-    raw_twist_rows<MT32P>(s, d, rows, stride, tid, nthr);
+__device__ void seed_state(W* x, const InitTask& t) {
+    if constexpr (std::is_same<W, uint32_t>::value) seed_mt32(x, t);
+    else if constexpr (std::is_same<W, uint64_t>::value) seed_mt64(x, t);
+    else seed_sfmt<N>(x, t);
 }
-template <>
-__device__ void twist_rows<uint64_t, 312>(const uint64_t* s, uint64_t* d, int rows, int stride, int tid, int nthr) {
-    raw_twist_rows<MT64P>(s, d, rows, stride, tid, nthr);
-}
-template <>
-__device__ void twist_rows<uint4, 156>(const uint4* s, uint4* d, int rows, int stride, int tid, int) {
-    raw_twist_rows_sfmt(s, d, rows, stride, tid);
+
+template <class W, int N>
+__device__ void twist_rows(const W* src, W* dst, int rows, int stride, int tid, int nthr) {
+    if constexpr (std::is_same<W, uint32_t>::value) raw_twist_rows<MT32P>(src, dst, rows, stride, tid, nthr);
+    else if constexpr (std::is_same<W, uint64_t>::value) raw_twist_rows<MT64P>(src, dst, rows, stride, tid, nthr);
+    else raw_twist_rows_sfmt<N>(src, dst, rows, stride, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,7 +985,7 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
     const uint32_t lane0 = g * G;
 
     if constexpr (INIT) {
-        if (tid == 0) seed_state<W>(buf, *init);
+        if (tid == 0) seed_state<W, N>(buf, *init);
     } else {
         for (int i = tid; i < N * G; i += nthr) {
             const int j = i / G, r = i - (i / G) * G;
@@ -1079,6 +1101,27 @@ static int lanes_per_group(uint32_t variant, uint32_t M) {
     return M < 16 ? (int)M : 16;
 }
 
+// SFMT variant -> its state size NN (the kernels' template parameter)
+#define VMT_SFMT_CASE(V, ...)                                                 \
+    case V: {                                                                 \
+        constexpr int NN = (int)kSfmtSets[V - kSFMT].n;                       \
+        __VA_ARGS__;                                                          \
+        break;                                                                \
+    }
+#define VMT_SFMT_SWITCH(variant, ...)                \
+    switch (variant) {                               \
+        VMT_SFMT_CASE(kSFMT607, __VA_ARGS__)         \
+        VMT_SFMT_CASE(kSFMT1279, __VA_ARGS__)        \
+        VMT_SFMT_CASE(kSFMT2281, __VA_ARGS__)        \
+        VMT_SFMT_CASE(kSFMT4253, __VA_ARGS__)        \
+        VMT_SFMT_CASE(kSFMT11213, __VA_ARGS__)       \
+        default: {                                   \
+            constexpr int NN = (int)kSfmtSets[0].n;  \
+            __VA_ARGS__;                             \
+            break;                                   \
+        }                                            \
+    }
+
 #define VMT_G_SWITCH(G, ...)                                 \
     switch (G) {                                             \
         case 1: { constexpr int GG = 1; __VA_ARGS__; break; } \
@@ -1110,7 +1153,7 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
     } else if (variant == kMT64) {
         VMT_G_SWITCH(G, init_kernel<uint64_t, 312, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant))
     } else {
-        VMT_G_SWITCH(G, init_kernel<uint4, 156, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant))
+        VMT_SFMT_SWITCH(variant, VMT_G_SWITCH(G, init_kernel<uint4, NN, GG><<<grid, block, 0, stream>>>(d_tasks, one, M, d_lane_polys, max_deg, variant)))
     }
     return hipGetLastError();
 }
@@ -1122,7 +1165,7 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
     // workgroup in 40 KB, so that many more lanes share each compute unit.
     const bool grouped = (uint64_t)count * M <= 1024;
     int G = lanes_per_group(variant, M);
-    const int cap = grouped ? 2 : (variant == kSFMT ? 4 : 8);
+    const int cap = grouped ? 2 : (is_sfmt(variant) ? 4 : 8);
     if (G > cap) G = cap;
     const dim3 grid(count * (M / G)), block(G * 64);
     if (grouped) {
@@ -1131,7 +1174,7 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
         } else if (variant == kMT64) {
             VMT_G2_SWITCH(G, jump_kernel<uint64_t, 312, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
         } else {
-            VMT_G2_SWITCH(G, jump_kernel<uint4, 156, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+            VMT_SFMT_SWITCH(variant, VMT_G2_SWITCH(G, jump_kernel<uint4, NN, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M)))
         }
     } else {
         if (variant == kMT32) {
@@ -1139,7 +1182,7 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
         } else if (variant == kMT64) {
             VMT_G8_SWITCH(G, jump_kernel<uint64_t, 312, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
         } else {
-            VMT_G8_SWITCH(G, jump_kernel<uint4, 156, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
+            VMT_SFMT_SWITCH(variant, VMT_G8_SWITCH(G, jump_kernel<uint4, NN, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M)))
         }
     }
     hipError_t e = hipGetLastError();
@@ -1186,9 +1229,9 @@ hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_k
     } else {
         const dim3 block(64);
         if (out_kind == kOutU32) {
-            VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<LL, 0><<<grid, block, 0, stream>>>(d_state, d_out, len, wp))
+            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_state, d_out, len, wp)))
         } else {
-            VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<LL, 1><<<grid, block, 0, stream>>>(d_state, d_out, len, wp))
+            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_state, d_out, len, wp)))
         }
     }
     hipError_t e = hipGetLastError();
@@ -1198,7 +1241,7 @@ hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_k
 }
 
 bool batch_supported(uint32_t variant, uint32_t M, int out_kind) {
-    if (variant == kSFMT) return false;
+    if (is_sfmt(variant)) return false;
     return generate_supported(variant, M, M, out_kind);
 }
 
@@ -1270,14 +1313,14 @@ uint32_t device_cus(int device) {
     return (uint32_t)cus;
 }
 
-hipError_t launch_batch_sfmt(uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks, uint32_t count,
-                             hipStream_t stream) {
+hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
+                             uint32_t count, hipStream_t stream) {
     if (count == 0) return hipSuccess;
     const dim3 grid(M / lpw, count), block(64);
     if (out_kind == kOutU32) {
-        VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<LL, 0><<<grid, block, 0, stream>>>(d_tasks))
+        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_tasks)))
     } else {
-        VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<LL, 1><<<grid, block, 0, stream>>>(d_tasks))
+        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_tasks)))
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || lpw == M) return e;

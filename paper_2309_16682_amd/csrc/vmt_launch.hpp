@@ -70,8 +70,8 @@ hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchS
 
 // Batched SFMT generation (one lane group of lpw lanes per workgroup, tasks
 // of one M); positions are maintained like launch_generate's.
-hipError_t launch_batch_sfmt(uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks, uint32_t count,
-                             hipStream_t stream);
+hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
+                             uint32_t count, hipStream_t stream);
 
 // Copy states: task i copies tasks[i].src to tasks[i].dst (bytes, a multiple of 16).
 hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream);

@@ -114,7 +114,7 @@ int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind
         // Single launches: lanes per workgroup, timed on at most 2^22 elements (their rate does not depend
         // on the length). Split calls: every chunk length giving 2 to 4096 chunks, timed on the full length.
         const uint64_t n = lens[0];
-        const uint64_t epw = variant == VMT_SFMT ? 4 : 1;
+        const uint64_t epw = vmt::is_sfmt(variant) ? 4 : 1;
         const uint64_t steps = (n + M * epw - 1) / (M * epw);
         auto call = [&](uint64_t len) -> hipError_t {
             int r = out_kind == VMT_OUT_U32   ? vmt_generate_u32(ctx, states, len, (uint32_t*)out, stream)
@@ -132,7 +132,7 @@ int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind
             sh.split_log2 = 255;
             shapes.push_back(sh);
         }
-        const bool can_split = variant == VMT_SFMT || vmt::batch_supported(variant, M, out_kind);
+        const bool can_split = vmt::is_sfmt(variant) || vmt::batch_supported(variant, M, out_kind);
         for (uint32_t v = 4; can_split && v <= 40; v++) {
             const uint64_t chunks = (steps + (1ull << v) - 1) >> v;
             if (chunks < 2) break;

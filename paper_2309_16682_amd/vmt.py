@@ -20,9 +20,14 @@ LIB_PATH = os.environ.get("VMT_LIBRARY") or os.path.join(PKG, "libvmt.so")
 VMT_OK = 0
 VMT_EINVAL, VMT_EVARIANT, VMT_ENOMEM, VMT_EDEVICE, VMT_EBUSY, VMT_ESTATE = -1, -2, -3, -4, -5, -6
 VMT_MT32, VMT_MT64, VMT_SFMT = 0, 1, 2
+# SFMT with the parameter sets of other Mersenne exponents (same recurrence)
+VMT_SFMT607, VMT_SFMT1279, VMT_SFMT2281, VMT_SFMT4253, VMT_SFMT11213 = 3, 4, 5, 6, 7
+SFMT_FAMILY = (VMT_SFMT, VMT_SFMT607, VMT_SFMT1279, VMT_SFMT2281, VMT_SFMT4253, VMT_SFMT11213)
+MEXP = {VMT_MT32: 19937, VMT_MT64: 19937, VMT_SFMT: 19937, VMT_SFMT607: 607, VMT_SFMT1279: 1279,
+        VMT_SFMT2281: 2281, VMT_SFMT4253: 4253, VMT_SFMT11213: 11213}
 VMT_OUT_U32, VMT_OUT_U64, VMT_OUT_F32, VMT_OUT_F64 = 0, 1, 2, 3
 
-STATE_WORDS = {VMT_MT32: 624, VMT_MT64: 312, VMT_SFMT: 156}
+STATE_WORDS = {VMT_MT32: 624, VMT_MT64: 312, **{v: MEXP[v] // 128 + 1 for v in SFMT_FAMILY}}
 
 
 class VmtError(RuntimeError):
@@ -385,10 +390,10 @@ def header(state_bytes: np.ndarray) -> dict:
 
 def window(state_bytes: np.ndarray, variant: int, M: int) -> np.ndarray:
     """The interleaved window of an exported state as (n, M) words
-    ((156, M, 4) uint32 for SFMT)."""
+    ((N, M, 4) uint32 for SFMT, N = 156 for SFMT19937)."""
     b = np.ascontiguousarray(state_bytes)[256:]
     if variant == VMT_MT32:
         return np.frombuffer(b.tobytes(), dtype=np.uint32).reshape(624, M)
     if variant == VMT_MT64:
         return np.frombuffer(b.tobytes(), dtype=np.uint64).reshape(312, M)
-    return np.frombuffer(b.tobytes(), dtype=np.uint32).reshape(156, M, 4)
+    return np.frombuffer(b.tobytes(), dtype=np.uint32).reshape(STATE_WORDS[variant], M, 4)

@@ -7,7 +7,8 @@ import numpy as np
 from oracle import pyoracle as O
 from tests import golden_io
 
-VARIANT_NAMES = {0: "mt32", 1: "mt64", 2: "sfmt"}
+VARIANT_NAMES = {0: "mt32", 1: "mt64", 2: "sfmt", 3: "sfmt607", 4: "sfmt1279", 5: "sfmt2281", 6: "sfmt4253",
+                 7: "sfmt11213"}
 
 
 def say(*a):
@@ -35,13 +36,13 @@ def oracle_prefix(variant, M, seed, count):
 def out_dtype(variant):
     import torch
 
-    return torch.int32 if variant in (0, 2) else torch.int64
+    return torch.int64 if variant == 1 else torch.int32  # MT19937-64: uint64; the others uint32
 
 
 def as_u(arr, variant):
     """torch int tensor (cpu) -> numpy unsigned view."""
     a = arr.numpy()
-    return a.view(np.uint32) if variant in (0, 2) else a.view(np.uint64)
+    return a.view(np.uint64) if variant == 1 else a.view(np.uint32)
 
 
 _POW2 = {}

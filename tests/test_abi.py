@@ -36,7 +36,9 @@ def test_host_only_context_and_error_paths():
         assert vmt.vmt_state_bytes(vmt.VMT_MT64, 8) == 256 + 312 * 8 * 8
         assert vmt.vmt_state_bytes(vmt.VMT_SFMT, 64) == 256 + 156 * 64 * 16
         assert vmt.vmt_state_bytes(vmt.VMT_MT32, 3) == 0
-        assert vmt.vmt_state_bytes(7, 4) == 0
+        assert vmt.vmt_state_bytes(vmt.VMT_SFMT607, 4) == 256 + 5 * 4 * 16
+        assert vmt.vmt_state_bytes(vmt.VMT_SFMT11213, 64) == 256 + 88 * 64 * 16
+        assert vmt.vmt_state_bytes(8, 4) == 0
         # device calls on a host-only context fail cleanly
         r = vmt.lib().vmt_init_genrand(ctx, 0, 1, 4, ctypes.c_void_p(256), None)
         assert r == vmt.VMT_EDEVICE
@@ -45,7 +47,7 @@ def test_host_only_context_and_error_paths():
         vmt.vmt_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_library_minpoly_equals_oracle_fixture(variant):
     from paper_2309_16682_amd import vmt
 
@@ -56,14 +58,15 @@ def test_library_minpoly_equals_oracle_fixture(variant):
         vmt.vmt_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_library_lane_polynomials_equal_oracle_fixtures(variant):
     from paper_2309_16682_amd import vmt
 
     ctx = vmt.vmt_ctx_create(-1)
     try:
         rows = golden_io.tpow2(variant)
-        for q in (19931, 19934, 19936):
+        mexp = golden_io.MEXP[variant]
+        for q in (mexp - 6, mexp - 3, mexp - 1, mexp):
             assert vmt.vmt_jump_poly(ctx, variant, 1 << q) == rows[q]
     finally:
         vmt.vmt_ctx_destroy(ctx)
@@ -75,7 +78,7 @@ def test_library_jump_poly_small_distances_match_oracle():
 
     ctx = vmt.vmt_ctx_create(-1)
     try:
-        for variant in (0, 1, 2):
+        for variant in (0, 1, 2, 3, 7):
             mu = golden_io.minpoly(variant)
             for d in (0, 1, 19936, 19937, 19968, 40000, 2**64 + 3, 3**50):
                 assert vmt.vmt_jump_poly(ctx, variant, d) == O.poly_powmod_t(d, mu), (variant, d)

@@ -1,4 +1,4 @@
-"""Pins of the linear-complexity self-check (Sec. 4: LinearComp; Sec. 3, eq.
+"""Pins of the linear-complexity self-check (Sec. 4.1: LinearComp; Sec. 3, eq.
 combseq; Sec. 3.1).
 
 The oracle's Berlekamp-Massey is pinned to closed forms (a known LFSR, the
@@ -137,7 +137,33 @@ def test_sfmt_vstream_bits_obey_phi_psiM(M):
 # ---- the library's polynomials ----------------------------------------------------
 
 
-@pytest.mark.parametrize("variant,M", [(0, 1), (0, 16), (1, 8), (2, 1), (2, 4), (2, 64)])
+@pytest.mark.parametrize("M,variant", [(4, O.SFMT607), (16, O.SFMT1279), (2, O.SFMT4253), (8, O.SFMT11213)])
+def test_sfmt_sets_vstream_bits_obey_check_poly(variant, M):
+    # The same collapse for the other SFMT parameter sets (phi here also holds
+    # the linear factors of mu: their roots satisfy alpha^(2^MEXP) = alpha too).
+    # A seeded state and one bit need not see every factor of psi, so the
+    # measured minimal polynomial divides A; it always holds the degree-MEXP
+    # factor (the certified state has a component along it).
+    A = check_poly(variant, M)
+    mexp = O.MEXP[variant]
+    frob = golden_io.tpow2(variant)[mexp]
+    g = O.poly_gcd(golden_io.minpoly(variant), frob ^ 2)
+    phi_p, rem = pdivmod(g, O.poly_gcd(g, 0b110))  # the irreducible factor of degree MEXP
+    assert rem == 0 and phi_p.bit_length() - 1 == mexp
+    n128 = 2 * (A.bit_length() - 1) + 100
+    u = vstream(variant, M, 1234, 4 * n128, skip=4 * 55).reshape(-1, 4)
+    for j, b in ((0, 0), (2, 21)):
+        p = O.berlekamp_massey(bit_seq(u[:, j], b))
+        assert pdivmod(A, p)[1] == 0, (variant, M, j, b)
+        assert pdivmod(p, phi_p)[1] == 0, (variant, M, j, b)
+    # with the lane spacing planted one step off, A no longer annihilates the stream
+    wrong = O.poly_mulmod(golden_io.lane_poly(variant, M), 2, golden_io.minpoly(variant))
+    w = vstream(variant, M, 1234, 4 * n128, lane_poly=wrong).reshape(-1, 4)
+    assert pdivmod(A, O.berlekamp_massey(bit_seq(w[:, 0], 0)))[1] != 0
+
+
+@pytest.mark.parametrize("variant,M", [(0, 1), (0, 16), (1, 8), (2, 1), (2, 4), (2, 64), (3, 4), (4, 16), (6, 2),
+                                       (7, 8)])
 def test_library_check_poly_equals_oracle(variant, M):
     from paper_2309_16682_amd import vmt
 
