@@ -46,10 +46,10 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # code (kernel_fingerprint) and launch shape they were taken with
 # (profiles/batch_mt32_m16_counters.md).
 COUNTERS = {
-    "kernel_fingerprint": "pending",
+    "kernel_fingerprint": "a7e8b475c850c4f2bc9ce022cea37b1ebd653690bc0a124297f5b5a53e446849",
     "shape": (512, 16, 2),  # threads per workgroup, store bytes, workgroups per CU
-    "read_bytes": 877962880,
-    "written_bytes": 96283548139,
+    "read_bytes": 877945856,
+    "written_bytes": 96283547883,
 }
 
 
@@ -550,6 +550,8 @@ def main():
             ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, "u32"),
             ("sfmt_M64_2^28_u32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "u32"),
             ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
+            ("sfmt607_M64_2^28_u32", vmt.VMT_SFMT607, 64, 1234, 1 << 28, "u32"),
+            ("sfmt11213_M16_2^28_u32", vmt.VMT_SFMT11213, 16, 1234, 1 << 28, "u32"),
         ):
             okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
             lpw = split = None
@@ -568,7 +570,7 @@ def main():
                   "f32": vmt.vmt_uniform_f32}[kind]
             fn(ctx, st, n, out)
             torch.cuda.synchronize()
-            reps = 2 if variant == vmt.VMT_SFMT and M == 4 else 3
+            reps = 2 if variant in vmt.SFMT_FAMILY and M <= 16 else 3
             e0.record()
             for _ in range(reps):
                 fn(ctx, st, n, out)
