@@ -8,12 +8,15 @@ oracle (tolerance 0).
            longest first over a 96 GiB arena), autotuned shape, launched from
            a captured HIP graph; 24 generators compared in full (the longest,
            the shortest and random ones) and the first 2000 outputs (or all)
-           of 40 more.
+           of 40 more; and every output of the round long enough to check
+           (more than 19,937 words) passes the linear-complexity check (each
+           bit obeys mu), a property that holds at any size.
   serving: 4,096 V-MT19937-64 (M = 8) states, the benchmark's trace (Poisson
            20k/s, 4 KiB - 256 MiB, 10 % jumps by 2^k) for its first 0.25 s,
            long requests split by jump-ahead, outputs retained; every request
-           completes, and sampled requests equal the oracle replaying their
-           state's history."""
+           completes, sampled requests equal the oracle replaying their
+           state's history, and every output long enough passes the
+           linear-complexity check."""
 import numpy as np
 import pytest
 
@@ -81,6 +84,17 @@ def test_batched_workload_first_round(ctx):
         i = int(i)
         n = min(2000, int(lens[i]))
         np.testing.assert_array_equal(out(i, n), oracle_stream(MT32, M, key=keys[i]).generate(n), err_msg=f"gen {i}")
+    # every checkable output of the round: the recurrence of its bits
+    checked = [i for i in idx if int(lens[i]) > 19937]
+    say(f"case batched workload: linear-complexity check of {len(checked)} outputs")
+    cnt = torch.full((len(checked),), -1, dtype=torch.int64, device="cuda")
+    for j, i in enumerate(checked):
+        n = int(lens[i])
+        vmt.vmt_check_stream(ctx, MT32, M, vmt.VMT_OUT_U32, arena[offs[i] : offs[i] + 4 * n], n, cnt[j : j + 1])
+    torch.cuda.synchronize()
+    bad = torch.nonzero(cnt).flatten().cpu().numpy()
+    assert len(checked) > 0.5 * len(idx)
+    assert bad.size == 0, [(checked[j], int(cnt[j])) for j in bad[:5]]
 
 
 def test_serving_workload_sampled(ctx):
@@ -126,3 +140,14 @@ def test_serving_workload_sampled(ctx):
         off = int(res[i]["out_offset"])
         got = as_u(arena[off : off + 8 * n].cpu().view(torch.int64), MT64)
         np.testing.assert_array_equal(got, ref.generate(n), err_msg=f"request {i} state {st} count {n}")
+    # every output long enough (more than 19,937 uint64 halves-pairs): the recurrence of its bits
+    checked = [i for i in gens if reqs[i][3] > 19937]
+    cnt = torch.full((len(checked),), -1, dtype=torch.int64, device="cuda")
+    for j, i in enumerate(checked):
+        off, n = int(res[i]["out_offset"]), reqs[i][3]
+        vmt.vmt_check_stream(ctx, MT64, M, vmt.VMT_OUT_U64, arena[off : off + 8 * n], n, cnt[j : j + 1])
+    torch.cuda.synchronize()
+    say(f"case serving workload: linear-complexity check of {len(checked)} outputs")
+    bad = torch.nonzero(cnt).flatten().cpu().numpy()
+    assert len(checked) > 0.3 * len(gens)
+    assert bad.size == 0, [(checked[j], int(cnt[j])) for j in bad[:5]]
