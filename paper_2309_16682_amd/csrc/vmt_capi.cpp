@@ -1088,7 +1088,7 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
         dev = c.dev;
     }
     hipError_t e = vmt::launch_check(out_kind, d_out, nw, S, dev, reinterpret_cast<unsigned long long*>(d_count),
-                                     8 * vmt::device_cus(ctx->device), stream);
+                                     vmt::device_cus(ctx->device), stream);
     if (e != hipSuccess) return hip_fail(e, "check kernel launch");
     return VMT_OK;
 }

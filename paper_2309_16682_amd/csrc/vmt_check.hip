@@ -12,26 +12,28 @@
 // over GF(2)). The S phases of the stride are independent sequences; a
 // workgroup takes a tile of kTile consecutive offsets of one phase and
 // stages the phase's words in LDS in chunks of kChunk coefficients
-// (kTile + kChunk words), the next chunk's global loads in flight while the
-// current chunk is worked on. Two forms, chosen by the density of A:
+// (kTile + kChunk words). Two forms, chosen by the density of A:
 //
 // Sparse (MT19937-32/-64: mu has 135 / 285 set coefficients of 19,938).
-// Thread t owns the offsets t + kThreads r, r < kR. For each set coefficient
-// i (a wave-uniform list) it XORs buf[i + t + kThreads r] into accumulator r:
+// 512 threads; thread t owns the offsets t + 512 r, r < 8. For each set coefficient
+// i (a wave-uniform list) it XORs buf[i + t + 512 r] into accumulator r:
 // consecutive lanes read consecutive words (conflict-free ds_read_b32), two
 // coefficients per three-input XOR. Every LDS byte read is used: the bound
 // is LDS bandwidth, 4 bytes per coefficient and offset.
 //
-// Dense (SFMT19937: phi psi^M has ~9,300 set coefficients). Thread t owns the
-// kR consecutive offsets kR t .. kR t + kR - 1, so one LDS window of kR + 32
-// words serves 32 coefficients. For each 32-coefficient word of A (a scalar
-// load, the next one in flight) a thread reads its window with ten
-// ds_read_b128 and, nibble by nibble, XORs the selected window words into its
-// accumulators: the nibble's value picks one of 16 straight-line cases (a
-// scalar branch), each combining up to four words per accumulator with
-// three-input XORs, ~1.25 VALU ops per nibble and accumulator. LDS layout:
-// word j sits in plane (j / 4) % 2 at 16-byte slot j / 8, so the window (five
-// 8-word groups) is ten 16-byte reads at a 16-byte lane stride.
+// Dense (SFMT19937: phi psi^M has ~9,300 set coefficients). 256 threads;
+// thread t owns the 16 consecutive offsets 16 t .. 16 t + 15, so one LDS
+// window of 48 words serves 32 coefficients. For each 32-coefficient word of
+// A (a scalar load, the next one in flight) a thread reads its window with
+// twelve ds_read_b128 and, nibble by nibble, XORs the selected window words
+// into its accumulators: the nibble's value picks one of 16 straight-line
+// cases (a scalar branch), each combining up to four words per accumulator
+// with three-input XORs, ~1.25 VALU ops per nibble and accumulator; sixteen
+// accumulators per thread amortise the branch. LDS layout: word j sits in
+// plane (j / 4) % 4 at 16-byte slot j / 16, so the window (three 16-word
+// groups) is twelve 16-byte reads at a 16-byte lane stride. (A sweep of
+// threads x offsets per thread on one MI355X: 256 x 16 ran in 0.70 of the
+// time of 512 x 8 and of 256 x 8 or 128 x 16.)
 #include <hip/hip_runtime.h>
 
 #include "vmt_launch.hpp"
@@ -39,14 +41,25 @@
 namespace vmt {
 namespace {
 
-constexpr int kThreads = 512;
-constexpr int kR = 8;                     // offsets per thread
-constexpr int kTile = kThreads * kR;      // offsets per workgroup tile
-constexpr int kChunk = kCheckChunkBits;   // coefficients staged per LDS fill
-constexpr int kBuf = kTile + kChunk;      // LDS words per fill
-constexpr int kPer = kBuf / kThreads;     // staged words per thread
-constexpr int kWin = kR + 32;             // dense window: words per 32 coefficients
-static_assert(kChunk % 32 == 0 && kR == 8 && kBuf % (4 * kThreads) == 0, "staging in 16-byte groups");
+constexpr int kChunk = kCheckChunkBits;  // coefficients staged per LDS fill
+
+// Launch geometry of the two forms; both tile 4096 offsets and stage
+// kTile + kChunk words per fill.
+template <bool DENSE>
+struct Form {
+    static constexpr int kThreads = DENSE ? 256 : 512;
+    static constexpr int kR = DENSE ? 16 : 8;                // offsets per thread
+    static constexpr int kTile = kThreads * kR;              // offsets per workgroup tile
+    static constexpr int kBuf = kTile + kChunk;              // LDS words per fill
+    static constexpr int kPer = kBuf / kThreads;             // staged words per thread
+    static constexpr int kPlanes = kR / 4;                   // dense layout: planes of 4-word slots
+    static constexpr int kWin = kR + 32;                     // dense window: words per 32 coefficients
+    static constexpr int kGridPerCu = DENSE ? 24 : 8;        // workgroups launched per CU
+    static_assert(kChunk % 32 == 0 && kBuf % (4 * kThreads) == 0 && 32 % kR == 0 && kR % 4 == 0,
+                  "staging in 16-byte groups; a 32-coefficient window is whole kR-word groups");
+};
+static_assert(Form<true>::kTile == Form<false>::kTile, "one tiling for both forms");
+constexpr int kTile = Form<true>::kTile;
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -57,15 +70,15 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 // ---- dense form: nibble cases ---------------------------------------------------
 
-// acc[r] ^= XOR over the set bits e of V of w[e + r], r < kR.
-template <int V>
-__device__ __forceinline__ void nibble(uint32_t (&acc)[kR], const uint32_t* w) {
+// acc[r] ^= XOR over the set bits e of V of w[e + r], r < R.
+template <int R, int V>
+__device__ __forceinline__ void nibble(uint32_t (&acc)[R], const uint32_t* w) {
     constexpr int n = __builtin_popcount(V);
     constexpr int e0 = V & 1 ? 0 : V & 2 ? 1 : V & 4 ? 2 : 3;                    // lowest set bit
     constexpr int e3 = V & 8 ? 3 : V & 4 ? 2 : V & 2 ? 1 : 0;                    // highest set bit
     constexpr int e1 = (V & ~(1 << e0)) & 2 ? 1 : (V & ~(1 << e0)) & 4 ? 2 : 3;  // second lowest
 #pragma unroll
-    for (int r = 0; r < kR; r++) {
+    for (int r = 0; r < R; r++) {
         if constexpr (n == 1) {
             acc[r] ^= w[e0 + r];
         } else if constexpr (n == 2) {
@@ -78,30 +91,36 @@ __device__ __forceinline__ void nibble(uint32_t (&acc)[kR], const uint32_t* w) {
     }
 }
 
-__device__ __forceinline__ void apply_nibble(uint32_t v, uint32_t (&acc)[kR], const uint32_t* w) {
+template <int R>
+__device__ __forceinline__ void apply_nibble(uint32_t v, uint32_t (&acc)[R], const uint32_t* w) {
     switch (v) {
-        case 1: nibble<1>(acc, w); break;
-        case 2: nibble<2>(acc, w); break;
-        case 3: nibble<3>(acc, w); break;
-        case 4: nibble<4>(acc, w); break;
-        case 5: nibble<5>(acc, w); break;
-        case 6: nibble<6>(acc, w); break;
-        case 7: nibble<7>(acc, w); break;
-        case 8: nibble<8>(acc, w); break;
-        case 9: nibble<9>(acc, w); break;
-        case 10: nibble<10>(acc, w); break;
-        case 11: nibble<11>(acc, w); break;
-        case 12: nibble<12>(acc, w); break;
-        case 13: nibble<13>(acc, w); break;
-        case 14: nibble<14>(acc, w); break;
-        case 15: nibble<15>(acc, w); break;
+        case 1: nibble<R, 1>(acc, w); break;
+        case 2: nibble<R, 2>(acc, w); break;
+        case 3: nibble<R, 3>(acc, w); break;
+        case 4: nibble<R, 4>(acc, w); break;
+        case 5: nibble<R, 5>(acc, w); break;
+        case 6: nibble<R, 6>(acc, w); break;
+        case 7: nibble<R, 7>(acc, w); break;
+        case 8: nibble<R, 8>(acc, w); break;
+        case 9: nibble<R, 9>(acc, w); break;
+        case 10: nibble<R, 10>(acc, w); break;
+        case 11: nibble<R, 11>(acc, w); break;
+        case 12: nibble<R, 12>(acc, w); break;
+        case 13: nibble<R, 13>(acc, w); break;
+        case 14: nibble<R, 14>(acc, w); break;
+        case 15: nibble<R, 15>(acc, w); break;
         default: break;
     }
 }
 
-// Dense LDS slot of buffer word j: two planes of 4-word groups.
-__device__ __forceinline__ uint32_t dense_slot(uint32_t j) {
-    return ((j >> 2) & 1) * (kBuf / 2) + (j >> 3) * 4 + (j & 3);
+// LDS slot of buffer word j. Dense: word j in plane (j / 4) % kPlanes at
+// 4-word slot j / kR (a thread's kR consecutive words are one slot in each
+// plane). Sparse: linear.
+template <bool DENSE>
+__device__ __forceinline__ uint32_t lds_slot(uint32_t j) {
+    using F = Form<DENSE>;
+    if constexpr (DENSE) return ((j >> 2) % F::kPlanes) * (F::kBuf / F::kPlanes) + (j / F::kR) * 4 + (j & 3);
+    else return j;
 }
 
 // ---- staging -------------------------------------------------------------------
@@ -127,15 +146,16 @@ __device__ __forceinline__ uint32_t stream_word(const void* src, uint64_t X) {
 // j = 4 (t + kThreads m): with S == 1, 32-bit elements and a 16-byte aligned
 // stream a group is one 16-byte load (base is a multiple of 4), otherwise
 // four word loads. Words at or beyond nk read as 0.
-template <int KIND>
+template <int KIND, bool DENSE>
 struct Stage {
-    uint32_t v[kPer];
+    using F = Form<DENSE>;
+    uint32_t v[F::kPer];
 
     __device__ __forceinline__ void fetch(const void* src, bool vec, uint32_t p, uint32_t S, uint64_t base,
                                           uint64_t nk, uint32_t t) {
 #pragma unroll
-        for (int m = 0; m < kPer / 4; m++) {
-            const uint64_t k = base + 4 * (t + kThreads * m);
+        for (int m = 0; m < F::kPer / 4; m++) {
+            const uint64_t k = base + 4 * (t + F::kThreads * m);
             if constexpr (KIND == kOutU32 || KIND == kOutF32) {
                 if (vec && k + 3 < nk) {
                     const uint4 u = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(src) + k);
@@ -159,12 +179,11 @@ struct Stage {
     }
 
     // The four words of a group are adjacent (and 16-byte aligned) in both layouts.
-    template <bool DENSE>
     __device__ __forceinline__ void store(uint32_t* buf, uint32_t t) const {
 #pragma unroll
-        for (int m = 0; m < kPer / 4; m++) {
-            const uint32_t j = 4 * (t + kThreads * m);
-            *reinterpret_cast<uint4*>(buf + (DENSE ? dense_slot(j) : j)) =
+        for (int m = 0; m < F::kPer / 4; m++) {
+            const uint32_t j = 4 * (t + F::kThreads * m);
+            *reinterpret_cast<uint4*>(buf + lds_slot<DENSE>(j)) =
                 make_uint4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
         }
     }
@@ -179,11 +198,12 @@ __global__ void zero_count_kernel(unsigned long long* count) { *count = 0; }
 // Sparse: E = the set coefficients in increasing order, E[Eoff[c] ..
 // Eoff[c + 1]) those of chunk c = [c kChunk, (c + 1) kChunk).
 template <int KIND, bool DENSE>
-__global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict__ src, uint64_t nw, uint32_t S,
-                                                        const uint32_t* __restrict__ A,
-                                                        const uint32_t* __restrict__ E,
-                                                        const uint32_t* __restrict__ Eoff, uint32_t deg,
-                                                        uint64_t tiles_per_phase, unsigned long long* count) {
+__global__ __launch_bounds__(Form<DENSE>::kThreads) void check_kernel(
+    const void* __restrict__ src, uint64_t nw, uint32_t S, const uint32_t* __restrict__ A,
+    const uint32_t* __restrict__ E, const uint32_t* __restrict__ Eoff, uint32_t deg, uint64_t tiles_per_phase,
+    unsigned long long* count) {
+    using F = Form<DENSE>;
+    constexpr int kR = F::kR, kThreads = F::kThreads, kBuf = F::kBuf;
     __shared__ __align__(16) uint32_t buf[kBuf];
     __shared__ unsigned long long wg_count;
     const uint32_t t = threadIdx.x;
@@ -192,47 +212,54 @@ __global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict_
     const bool vec = S == 1 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
     const uint32_t n_chunks = deg / kChunk + 1;
     const uint64_t tiles = tiles_per_phase * S;
-    Stage<KIND> st;
+    Stage<KIND, DENSE> st;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const uint32_t p = (uint32_t)(tile / tiles_per_phase);
         const uint64_t k0 = (tile % tiles_per_phase) * kTile;
         const uint64_t nk = nw > p ? (nw - p + S - 1) / S : 0;  // words in phase p
         const uint64_t valid = nk > deg ? nk - deg : 0;          // offsets k < valid are checked
         if (k0 >= valid) continue;                               // the same for the whole workgroup
-        uint32_t acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-        st.fetch(src, vec, p, S, k0, nk, t);
+        uint32_t acc[kR];
+#pragma unroll
+        for (int r = 0; r < kR; r++) acc[r] = 0;
+        // Sparse: the next chunk's loads are in flight while this chunk is worked on.
+        // Dense (ALU-bound): loaded right before the store, so the staging
+        // registers are free during the XOR loop (occupancy).
+        if constexpr (!DENSE) st.fetch(src, vec, p, S, k0, nk, t);
         for (uint32_t c = 0; c < n_chunks; c++) {
             const uint32_t i0 = c * kChunk;
+            if constexpr (DENSE) st.fetch(src, vec, p, S, k0 + i0, nk, t);
             __syncthreads();  // the previous chunk's reads are done
-            st.template store<DENSE>(buf, t);
+            st.store(buf, t);
             __syncthreads();
-            if (c + 1 < n_chunks) st.fetch(src, vec, p, S, k0 + i0 + kChunk, nk, t);  // in flight meanwhile
+            if constexpr (!DENSE) {
+                if (c + 1 < n_chunks) st.fetch(src, vec, p, S, k0 + i0 + kChunk, nk, t);
+            }
             if constexpr (DENSE) {
                 const uint32_t* Ac = A + i0 / 32;
                 uint32_t a = uniform(Ac[0]);
                 for (int q = 0; q < kChunk / 32; q++) {
                     const uint32_t a_next = q + 1 < kChunk / 32 ? uniform(Ac[q + 1]) : 0u;
                     if (a != 0) {
-                        // window: buffer words 32 q + kR t + 0 .. kWin - 1 = 8-word groups
-                        // 4 q + t .. 4 q + t + 4; the last word is
-                        // 32 (kChunk/32 - 1) + kR (kThreads - 1) + kWin - 1 = kBuf - 1
-                        const uint4* lo = reinterpret_cast<const uint4*>(buf) + 4 * q + t;
-                        const uint4* hi = reinterpret_cast<const uint4*>(buf + kBuf / 2) + 4 * q + t;
-                        uint32_t w[kWin];
+                        // window: buffer words 32 q + kR t + 0 .. kWin - 1 = kR-word groups
+                        // g0 .. g0 + kWin / kR - 1, g0 = 32 q / kR + t; the last group is
+                        // 32 (kChunk/32 - 1) / kR + (kThreads - 1) + kWin / kR - 1 = kBuf / kR - 1
+                        const uint32_t g0 = 32 * q / kR + t;
+                        uint32_t w[F::kWin];
 #pragma unroll
-                        for (int m = 0; m < kWin / 8; m++) {
-                            const uint4 u = lo[m], v = hi[m];
-                            w[8 * m] = u.x;
-                            w[8 * m + 1] = u.y;
-                            w[8 * m + 2] = u.z;
-                            w[8 * m + 3] = u.w;
-                            w[8 * m + 4] = v.x;
-                            w[8 * m + 5] = v.y;
-                            w[8 * m + 6] = v.z;
-                            w[8 * m + 7] = v.w;
+                        for (int m = 0; m < F::kWin / kR; m++) {
+#pragma unroll
+                            for (int pl = 0; pl < F::kPlanes; pl++) {
+                                const uint4 u =
+                                    reinterpret_cast<const uint4*>(buf + pl * (kBuf / F::kPlanes))[g0 + m];
+                                w[kR * m + 4 * pl] = u.x;
+                                w[kR * m + 4 * pl + 1] = u.y;
+                                w[kR * m + 4 * pl + 2] = u.z;
+                                w[kR * m + 4 * pl + 3] = u.w;
+                            }
                         }
 #pragma unroll
-                        for (int n = 0; n < 8; n++) apply_nibble((a >> (4 * n)) & 15u, acc, w + 4 * n);
+                        for (int n = 0; n < 8; n++) apply_nibble<kR>((a >> (4 * n)) & 15u, acc, w + 4 * n);
                     }
                     a = a_next;
                 }
@@ -265,33 +292,38 @@ __global__ __launch_bounds__(kThreads) void check_kernel(const void* __restrict_
     if (t == 0 && wg_count) atomicAdd(count, wg_count);
 }
 
-template <int KIND>
-void launch_kind(const CheckPolyDev& poly, uint32_t grid, hipStream_t stream, const void* src, uint64_t nw,
-                 uint32_t S, uint64_t tpp, unsigned long long* count) {
-    if (poly.dense)
-        check_kernel<KIND, true><<<grid, kThreads, 0, stream>>>(src, nw, S, poly.bits, poly.terms, poly.term_off,
+template <int KIND, bool DENSE>
+void launch_form(const CheckPolyDev& poly, uint64_t tiles, uint32_t cus, hipStream_t stream, const void* src,
+                 uint64_t nw, uint32_t S, uint64_t tpp, unsigned long long* count) {
+    using F = Form<DENSE>;
+    const uint64_t cap = (uint64_t)F::kGridPerCu * cus;
+    const uint32_t grid = (uint32_t)(tiles < cap ? tiles : cap);
+    check_kernel<KIND, DENSE><<<grid, F::kThreads, 0, stream>>>(src, nw, S, poly.bits, poly.terms, poly.term_off,
                                                                poly.deg, tpp, count);
-    else
-        check_kernel<KIND, false><<<grid, kThreads, 0, stream>>>(src, nw, S, poly.bits, poly.terms, poly.term_off,
-                                                                poly.deg, tpp, count);
+}
+
+template <int KIND>
+void launch_kind(const CheckPolyDev& poly, uint64_t tiles, uint32_t cus, hipStream_t stream, const void* src,
+                 uint64_t nw, uint32_t S, uint64_t tpp, unsigned long long* count) {
+    if (poly.dense) launch_form<KIND, true>(poly, tiles, cus, stream, src, nw, S, tpp, count);
+    else launch_form<KIND, false>(poly, tiles, cus, stream, src, nw, S, tpp, count);
 }
 
 }  // namespace
 
 hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const CheckPolyDev& poly,
-                        unsigned long long* d_count, uint32_t max_grid, hipStream_t stream) {
+                        unsigned long long* d_count, uint32_t cus, hipStream_t stream) {
     zero_count_kernel<<<1, 1, 0, stream>>>(d_count);
     const uint64_t nk0 = (nw + S - 1) / S;  // phase 0 is the longest
     const uint64_t valid0 = nk0 > poly.deg ? nk0 - poly.deg : 0;
     const uint64_t tiles_per_phase = (valid0 + kTile - 1) / kTile;
     const uint64_t tiles = tiles_per_phase * S;
     if (tiles == 0) return hipGetLastError();
-    const uint32_t grid = (uint32_t)(tiles < max_grid ? tiles : max_grid);
     switch (out_kind) {
-        case kOutU32: launch_kind<kOutU32>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
-        case kOutF32: launch_kind<kOutF32>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
-        case kOutU64: launch_kind<kOutU64>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
-        default: launch_kind<kOutF64>(poly, grid, stream, src, nw, S, tiles_per_phase, d_count); break;
+        case kOutU32: launch_kind<kOutU32>(poly, tiles, cus, stream, src, nw, S, tiles_per_phase, d_count); break;
+        case kOutF32: launch_kind<kOutF32>(poly, tiles, cus, stream, src, nw, S, tiles_per_phase, d_count); break;
+        case kOutU64: launch_kind<kOutU64>(poly, tiles, cus, stream, src, nw, S, tiles_per_phase, d_count); break;
+        default: launch_kind<kOutF64>(poly, tiles, cus, stream, src, nw, S, tiles_per_phase, d_count); break;
     }
     return hipGetLastError();
 }

@@ -59,8 +59,9 @@ struct CheckPolyDev {
     const uint32_t* terms = nullptr;   // set coefficients, increasing
     const uint32_t* term_off = nullptr;  // deg / kCheckChunkBits + 2 entries: terms of chunk c start at term_off[c]
 };
+// cus: compute units of the device (the grid is a few workgroups per CU).
 hipError_t launch_check(int out_kind, const void* src, uint64_t nw, uint32_t S, const CheckPolyDev& poly,
-                        unsigned long long* d_count, uint32_t max_grid, hipStream_t stream);
+                        unsigned long long* d_count, uint32_t cus, hipStream_t stream);
 
 // Persistent batched generation. d_counter points to two uint32 that must be
 // zero before the first launch (reset_counters); every launch leaves them zero.
