@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving section only")
     ap.add_argument("--only-check", action="store_true", help="run the linear-complexity self-check section only")
+    ap.add_argument("--only-single", type=str, default=None,
+                    help="run these single-stream configurations only (comma-separated names, e.g. sfmt_M4_2^28_u32)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="launch the rounds eagerly instead of replaying a graph")
     ap.add_argument("--tune-sample", type=int, default=8192)
@@ -203,6 +205,64 @@ def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
 # word from LDS, 256 CUs x 128 B/clock x 2.4 GHz = 78.6 TB/s.
 CHECK_PEAK_TERMS = 2 * 256 * 4 * 16 * 2.4e9
 LDS_PEAK_BYTES = 256 * 128 * 2.4e9
+
+
+SINGLE_STREAMS = (
+    ("mt32_M16_2^24_u32", 0, 16, 5489, 1 << 24, "u32"),
+    ("mt32_M1_2^24_u32 (the std::mt19937 stream)", 0, 1, 5489, 1 << 24, "u32"),
+    ("mt64_M8_2^26_u64", 1, 8, 5489, 1 << 26, "u64"),
+    ("mt64_M8_2^26_f64", 1, 8, 5489, 1 << 26, "f64"),
+    ("sfmt_M4_2^28_u32", 2, 4, 1234, 1 << 28, "u32"),
+    ("sfmt_M64_2^28_u32", 2, 64, 1234, 1 << 28, "u32"),
+    ("sfmt_M64_2^28_f32", 2, 64, 1234, 1 << 28, "f32"),
+    ("sfmt607_M64_2^28_u32", 3, 64, 1234, 1 << 28, "u32"),
+    ("sfmt11213_M16_2^28_u32", 7, 16, 1234, 1 << 28, "u32"),
+)
+
+
+def single_streams(ctx, torch, args, only=None) -> dict:
+    """Workloads 1-3 (one generator each, after autotuning the generate family):
+    output GB/s of one call of n elements, state resident in HBM."""
+    from paper_2309_16682_amd import vmt
+
+    dev = torch.device("cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sec = {}
+    for name, variant, M, seed, n, kind in SINGLE_STREAMS:
+        if only and name.split(" ")[0] not in only:
+            continue
+        okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
+        lpw = split = None
+        if not args.no_autotune:
+            b, tried = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [n], reps=2)
+            lpw = b.lanes_per_wg
+            split = b.split_log2
+            log(f"{name} autotune: " + ", ".join(
+                f"{'lpw=%d' % t.lanes_per_wg if t.split_log2 == 255 else 'split=2^%d' % t.split_log2}: "
+                f"{t.gbps:.1f}" for t in tried))
+        st = vmt.new_state(variant, M)
+        vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+        esz = 8 if kind in ("u64", "f64") else 4
+        out = torch.empty(n * esz, dtype=torch.uint8, device=dev)
+        fn = {"u32": vmt.vmt_generate_u32, "u64": vmt.vmt_generate_u64, "f64": vmt.vmt_uniform_f64,
+              "f32": vmt.vmt_uniform_f32}[kind]
+        fn(ctx, st, n, out)
+        torch.cuda.synchronize()
+        reps = 2 if variant in vmt.SFMT_FAMILY and M <= 16 else 3
+        e0.record()
+        for _ in range(reps):
+            fn(ctx, st, n, out)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3 / reps
+        shp = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind)
+        sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3),
+                     "lanes_per_wg": shp.lanes_per_wg,
+                     "split": "never" if shp.split_log2 == 255 else (
+                         "auto" if shp.split_log2 == 0 else f"chunks of 2^{shp.split_log2} lane steps")}
+        log(f"{name}: {sec[name]}")
+        del out
+    return sec
 
 
 def self_check(ctx, torch, reps: int = 3) -> dict:
@@ -336,6 +396,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.calibrate:
         print(json.dumps(calibrate(torch)), flush=True)
+        return
+    if args.only_single:
+        ctx = vmt.vmt_ctx_create(0)
+        print(json.dumps({"single_stream": single_streams(ctx, torch, args, args.only_single.split(","))}), flush=True)
+        vmt.vmt_ctx_destroy(ctx)
         return
     if args.only_check:
         ctx = vmt.vmt_ctx_create(0)
@@ -539,52 +604,8 @@ def main():
 
     # ---- single-stream configurations (one generator each)
     if not args.skip_secondary:
-        sec = {}
-        arena = None
         torch.cuda.empty_cache()
-        for name, variant, M, seed, n, kind in (
-            ("mt32_M16_2^24_u32", vmt.VMT_MT32, 16, 5489, 1 << 24, "u32"),
-            ("mt32_M1_2^24_u32 (the std::mt19937 stream)", vmt.VMT_MT32, 1, 5489, 1 << 24, "u32"),
-            ("mt64_M8_2^26_u64", vmt.VMT_MT64, 8, 5489, 1 << 26, "u64"),
-            ("mt64_M8_2^26_f64", vmt.VMT_MT64, 8, 5489, 1 << 26, "f64"),
-            ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, "u32"),
-            ("sfmt_M64_2^28_u32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "u32"),
-            ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
-            ("sfmt607_M64_2^28_u32", vmt.VMT_SFMT607, 64, 1234, 1 << 28, "u32"),
-            ("sfmt11213_M16_2^28_u32", vmt.VMT_SFMT11213, 16, 1234, 1 << 28, "u32"),
-        ):
-            okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
-            lpw = split = None
-            if not args.no_autotune:
-                b, tried = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [n], reps=2)
-                lpw = b.lanes_per_wg
-                split = b.split_log2
-                log(f"{name} autotune: " + ", ".join(
-                    f"{'lpw=%d' % t.lanes_per_wg if t.split_log2 == 255 else 'split=2^%d' % t.split_log2}: "
-                    f"{t.gbps:.1f}" for t in tried))
-            st = vmt.new_state(variant, M)
-            vmt.vmt_init_genrand(ctx, variant, seed, M, st)
-            esz = 8 if kind in ("u64", "f64") else 4
-            out = torch.empty(n * esz, dtype=torch.uint8, device=dev)
-            fn = {"u32": vmt.vmt_generate_u32, "u64": vmt.vmt_generate_u64, "f64": vmt.vmt_uniform_f64,
-                  "f32": vmt.vmt_uniform_f32}[kind]
-            fn(ctx, st, n, out)
-            torch.cuda.synchronize()
-            reps = 2 if variant in vmt.SFMT_FAMILY and M <= 16 else 3
-            e0.record()
-            for _ in range(reps):
-                fn(ctx, st, n, out)
-            e1.record()
-            torch.cuda.synchronize()
-            s = e0.elapsed_time(e1) * 1e-3 / reps
-            shp = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind)
-            sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3),
-                         "lanes_per_wg": shp.lanes_per_wg,
-                         "split": "never" if shp.split_log2 == 255 else (
-                             "auto" if shp.split_log2 == 0 else f"chunks of 2^{shp.split_log2} lane steps")}
-            log(f"{name}: {sec[name]}")
-            del out
-        result["single_stream"] = sec
+        result["single_stream"] = single_streams(ctx, torch, args)
         result["self_check"] = self_check(ctx, torch)
 
     arena = out_base = None  # the batch arena is not needed any more

@@ -191,8 +191,15 @@ __device__ __forceinline__ uint64_t temper(uint64_t y) {
 // quad splits each step four ways instead: the two shifts that cross
 // sub-words take the neighbour's value by a quad permutation (DPP). The
 // neighbour's part of w_{k+N-2} is exchanged two steps ahead, off the
-// dependency chain, and the next step's loads are issued before this step's
-// store.
+// dependency chain.
+//
+// The block loop is unrolled and software-pipelined: the operands w_k and
+// w_{k+MM} of the old block are loaded kPrefetch steps ahead, and the new
+// words that the recurrence reads again (w_{k+MM} for k + MM >= N, written
+// N - MM steps before) stay in registers. So no load waits for the step just
+// stored: the critical path of a step is the recurrence itself (the shift of
+// w_{k+N-1} and an XOR). (A chain that loads each operand right before use
+// waits for an LDS round trip per step, ~200 cycles.)
 __device__ __forceinline__ uint32_t quad_next(uint32_t x) {  // value of quad thread j + 1 (j = 3: own)
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xF9, 0xF, 0xF, false);
 }
@@ -200,35 +207,46 @@ __device__ __forceinline__ uint32_t quad_prev(uint32_t x) {  // value of quad th
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x90, 0xF, 0xF, false);
 }
 
-// src, dst: sub-word j of word k at [k * ws + j] (u32 units). src == dst runs
-// in place (word k is read before it is written; w_{k+MM} for k + MM >= N is a
-// new word written N - MM >= 2 steps earlier by this same thread).
-// emit(k, value) is called for every new sub-word in order.
+constexpr int kPrefetch = 8;  // steps between an operand load and its use
+
+// src, dst: sub-word j of word k at [k * ws + j] (u32 units); src == dst runs
+// in place (every old word is loaded before the step that overwrites it).
+// The four threads of a quad must run it together. emit(k, value) is called
+// for every new sub-word in order.
 template <int N, class Emit>
 __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* dst, int ws, int j, Emit emit) {
     using P = SfmtP<N>;
     constexpr int MM = P::MM;
+    constexpr int PD = kPrefetch < N ? kPrefetch : N;
     // the mask K of eq. (sfmt_params), sub-word j
     const uint32_t K = j == 0 ? P::K0 : j == 1 ? P::K1 : j == 2 ? P::K2 : P::K3;
     const uint32_t lo_mask = j ? ~0u : 0u;  // sub-word 0 has no lower neighbour
     const uint32_t hi_mask = j < 3 ? ~0u : 0u;  // sub-word 3 has no upper neighbour
+    // all indices below are compile-time constants after unrolling: the arrays are registers,
+    // and only the live window of each (PD loads ahead, N - MM new words back) occupies any
+    uint32_t pa[N], pb[N], nw[N];
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+        pa[k] = src[k * ws + j];
+        if (k + MM < N) pb[k] = src[(k + MM) * ws + j];
+    }
     // cn, dn: the upper neighbour's sub-word of c and d, zero for sub-word 3
     uint32_t c = src[(N - 2) * ws + j], d = src[(N - 1) * ws + j];
     uint32_t cn = quad_next(c) & hi_mask, dn = quad_next(d) & hi_mask;
-    uint32_t a = src[j], b = src[MM * ws + j];
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < N; ++k) {
-        const uint32_t ak = a, bk = b;
-        if (k + 1 < N) {  // next step's operands (never written by this step)
-            a = src[(k + 1) * ws + j];
-            b = k + 1 + MM < N ? src[(k + 1 + MM) * ws + j] : dst[(k + 1 + MM - N) * ws + j];
+        if (k + PD < N) {  // operands of step k + PD: old words, not yet overwritten
+            pa[k + PD] = src[(k + PD) * ws + j];
+            if (k + PD + MM < N) pb[k + PD] = src[(k + PD + MM) * ws + j];
         }
+        const uint32_t ak = pa[k], bk = k + MM < N ? pb[k] : nw[k + MM - N];
         // (a <<< SL2) and (c >>> SR2) on this sub-word: funnel shifts with the neighbour's sub-word
         const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak) & lo_mask, 32 - P::SL2);
         const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, P::SR2);
         uint32_t r = xor3(ak, al, cr);
         r = xor_and(r, bk >> P::SR1, K);
         r ^= d << P::SL1;
+        nw[k] = r;
         dst[k * ws + j] = r;
         emit(k, r);
         c = d;
@@ -655,19 +673,18 @@ struct SfmtGen {
         if (q < LPW) {
             for (uint64_t b = 0; b < nblocks; ++b) {
                 const uint64_t o0 = head + b * B;
-                OutT* ob = out + o0;
                 const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
-                const uint32_t base = 4u * (lane0 + q) + j;  // output index of word 0's sub-word j
-                if (lim == B) {
-                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
-                        ob[base + 4u * M * k] = map(r);
-                    });
-                } else {
-                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int k, uint32_t r) {
-                        const uint32_t o = base + 4u * M * k;
-                        if (o < lim) ob[o] = map(r);
-                    });
-                }
+                // output of word k's sub-word j: out[o0 + base + 4 M k], a running pointer. The
+                // stride is re-read in every block (readfirstlane is not hoisted out of the loop):
+                // otherwise the compiler keeps the N per-step offsets live across blocks.
+                const uint32_t step = __builtin_amdgcn_readfirstlane(4u * M);
+                uint32_t o = 4u * (lane0 + q) + j;
+                OutT* op = out + o0 + o;
+                sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
+                    if (o < lim) *op = map(r);
+                    o += step;
+                    op += step;
+                });
             }
         }
         __syncthreads();
@@ -775,7 +792,7 @@ __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int 
     const int row = tid >> 2, j = tid & 3;  // one quad of threads per row
     if (row >= rows) return;
     sfmt_block_quad<N>(reinterpret_cast<const uint32_t*>(src + row * stride), reinterpret_cast<uint32_t*>(dst + row * stride),
-                    4, j, [](int, uint32_t) {});
+                       4, j, [](int, uint32_t) {});
 }
 
 __device__ __forceinline__ uint32_t xorw(uint32_t a, uint32_t b) { return a ^ b; }
