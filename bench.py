@@ -43,13 +43,15 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 
 # HBM bytes per launch of the batch kernel from rocprofv3 FETCH_SIZE (x2.0) and
 # WRITE_SIZE (x1.0), scaled by a 4 GiB device copy; valid only for the kernel
-# code (kernel_fingerprint) and launch shape they were taken with
-# (profiles/batch_mt32_m16_counters.md).
+# code (kernel_fingerprint) and the launch shapes they were taken with
+# (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
+# workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "a7e8b475c850c4f2bc9ce022cea37b1ebd653690bc0a124297f5b5a53e446849",
-    "shape": (512, 16, 2),  # threads per workgroup, store bytes, workgroups per CU
-    "read_bytes": 877945856,
-    "written_bytes": 96283547883,
+    "kernel_fingerprint": "76833bc923b9c4b560b50abb8afa5a77b9dbe3296cee55e26cb98c6ff9c934a8",
+    "shapes": {
+        (512, 16, 2): (878112683, 96283548149),
+        (512, 8, 2): (878247979, 96283547797),
+    },
 }
 
 
@@ -67,10 +69,10 @@ def kernel_fingerprint() -> str:
 
 
 def counter_traffic(shape) -> int | None:
-    if kernel_fingerprint() != COUNTERS["kernel_fingerprint"] or (
-        shape.threads, shape.store_bytes, shape.wg_per_cu) != COUNTERS["shape"]:
+    key = (shape.threads, shape.store_bytes, shape.wg_per_cu)
+    if kernel_fingerprint() != COUNTERS["kernel_fingerprint"] or key not in COUNTERS["shapes"]:
         return None
-    return COUNTERS["read_bytes"] + COUNTERS["written_bytes"]
+    return sum(COUNTERS["shapes"][key])
 
 
 def log(*a):
@@ -179,14 +181,26 @@ def cpu_baseline(seconds: float, threads: int) -> dict:
 
 
 def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
-    """A plain device copy (read n + write n bytes) and fill (write n bytes)
-    of `gib` GiB: their FETCH_SIZE / WRITE_SIZE readings give the counters'
-    scale, their rate the write ceiling measured on this device."""
+    """A plain device copy (read n + write n bytes), fill (torch's 16-byte
+    vector stores) and hipMemsetAsync (write n bytes) of `gib` GiB: the copy's
+    FETCH_SIZE / WRITE_SIZE readings give the counters' scale, the fill and
+    memset rates the write ceiling measured on this device."""
     n = gib << 30
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty(n, dtype=torch.uint8, device="cuda")
     out = {"bytes": n}
-    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * n), ("fill", lambda: dst.fill_(7), n)):
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")  # the HIP runtime torch has loaded
+    hip.hipMemsetAsync.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
+    hip.hipMemsetAsync.restype = ctypes.c_int
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def memset():
+        assert hip.hipMemsetAsync(ctypes.c_void_p(dst.data_ptr()), 7, n, stream) == 0
+
+    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * n), ("fill", lambda: dst.fill_(7), n),
+                            ("memset", memset, n)):
         fn()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -560,6 +574,7 @@ def main():
             "kernel": "batch_mt_kernel<MT32, 16 lanes, u32>",
             "avg_launch_ms": round(launch_ms_mean, 4),
             "measured_fill_GBps": ceiling["fill_GBps"],
+            "measured_memset_GBps": ceiling["memset_GBps"],
             "frac_of_measured_fill": round(achieved / ceiling["fill_GBps"], 4),
             "alg_bytes_per_launch": int(np.mean(round_alg_bytes)),
         },
