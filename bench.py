@@ -279,6 +279,35 @@ def single_streams(ctx, torch, args, only=None) -> dict:
     return sec
 
 
+def call_size_sweep(ctx, torch) -> dict:
+    """Workload 1's call-size sweep: one V-MT19937-32 (M = 16) state, calls of
+    1 .. 2^20 elements (powers of 4), each timed over repeated back-to-back
+    calls: per-call time (launch overhead at the small end) and output GB/s."""
+    from paper_2309_16682_amd import vmt
+
+    # the default shape (lanes per workgroup and splitting chosen per call), not one tuned for 2^24 elements
+    vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, vmt.VMT_MT32, 16, vmt.VMT_OUT_U32)
+    st = vmt.new_state(vmt.VMT_MT32, 16)
+    vmt.vmt_init_genrand(ctx, vmt.VMT_MT32, 7, 16, st)
+    out = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for lg in range(0, 21, 2):
+        n = 1 << lg
+        reps = 200 if n <= 4096 else 50
+        vmt.vmt_generate_u32(ctx, st, n, out)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            vmt.vmt_generate_u32(ctx, st, n, out)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res[f"2^{lg}"] = {"us_per_call": round(us, 2), "GB/s": round(4 * n / us / 1e3, 3)}
+    log(f"call-size sweep: {res}")
+    return res
+
+
 def self_check(ctx, torch, reps: int = 3) -> dict:
     """Time vmt_check_stream on single streams: term-XORs = set coefficients x checked offsets."""
     from paper_2309_16682_amd import vmt
@@ -413,7 +442,8 @@ def main():
         return
     if args.only_single:
         ctx = vmt.vmt_ctx_create(0)
-        print(json.dumps({"single_stream": single_streams(ctx, torch, args, args.only_single.split(","))}), flush=True)
+        print(json.dumps({"single_stream": single_streams(ctx, torch, args, args.only_single.split(",")),
+                          "call_size_sweep_mt32_M16": call_size_sweep(ctx, torch)}), flush=True)
         vmt.vmt_ctx_destroy(ctx)
         return
     if args.only_check:
@@ -621,6 +651,7 @@ def main():
     if not args.skip_secondary:
         torch.cuda.empty_cache()
         result["single_stream"] = single_streams(ctx, torch, args)
+        result["call_size_sweep_mt32_M16"] = call_size_sweep(ctx, torch)
         result["self_check"] = self_check(ctx, torch)
 
     arena = out_base = None  # the batch arena is not needed any more
