@@ -235,6 +235,18 @@ vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_stat
  * the duration of the run. Blocks until every request has completed. */
 int vmt_server_run(vmt_server* server, const vmt_request* reqs, size_t n, vmt_result* results, int realtime,
                    double* wall_s);
+/* Bound on how long a run may go with work in flight and no request
+ * completing (default 30 s; 0 <= seconds < inf, else VMT_EINVAL). When it is
+ * reached the run gives up: it drains its streams and returns VMT_EBUSY, and
+ * every request that had not completed gets status VMT_EBUSY. Of those, a
+ * request with launch >= 0 had tasks launched, which have all run by the time
+ * the call returns; one with launch = -1 never started and left its state
+ * untouched. A generation request served by one task (no chunking or
+ * splitting) with launch >= 0 has therefore written its whole output and
+ * advanced its state past it; a chunked or split one may stop part-way.
+ * seconds = 0 gives up at the first check with anything in flight, which
+ * forces this path from the host. The server stays usable. */
+int vmt_server_set_watchdog(vmt_server* server, double seconds);
 int vmt_server_destroy(vmt_server* server);
 
 /* Forget a state: the context's registry is keyed by device address, so a

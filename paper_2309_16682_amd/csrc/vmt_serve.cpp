@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -116,6 +117,7 @@ struct vmt_server {
     bool split = false;
     uint64_t budget = 0;
     uint64_t chunk = 0;  // elements per generation task (0: whole request)
+    double watchdog_s = 30.0;  // a run gives up after this long with work in flight and no completion
     std::vector<uint8_t*> states;
     uint8_t* arena = nullptr;
     uint64_t capacity = 0;
@@ -348,7 +350,8 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
     const auto t0 = Clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(Clock::now() - t0).count(); };
     double last_progress = 0.0;
-    const double watchdog_s = 30.0;  // no completion for this long with work in flight: give up
+    const double watchdog_s = s->watchdog_s;
+    std::vector<uint8_t> completed(n, 0);
     auto mark_launch = [&](uint32_t r) {
         if (res[r].launch < 0) {
             res[r].t_launch = now_s();
@@ -361,7 +364,7 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
         bool progress = false;
         bool any_inflight = !inflight.empty();
         for (auto& q : fifo) any_inflight = any_inflight || !q.empty();
-        if (any_inflight && t - last_progress > watchdog_s) {
+        if (any_inflight && t - last_progress >= watchdog_s) {
             err = vmt::set_error(VMT_EBUSY, "serving watchdog: no request completed for %.0f s", watchdog_s);
             break;
         }
@@ -381,6 +384,7 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
                 }
             }
             res[r].t_done = now_s();
+            completed[r] = 1;
             if (reqs[r].kind == 0) arena.release(res[r].out_offset, reqs[r].count * s->elem);
             for (uint32_t sl : slot_of[r]) free_slots.push_back(sl);
             slot_of[r].clear();
@@ -582,6 +586,9 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
     }
     const double wall = now_s();
     for (auto st : s->streams) (void)hipStreamSynchronize(st);
+    if (err != VMT_OK)  // the run gave up: what it launched has run (the streams are drained), the rest has not
+        for (size_t i = 0; i < n; i++)
+            if (res[i].status == VMT_OK && !completed[i]) res[i].status = err;
     (void)hipHostFree(flags);
     if (d_plain) {
         (void)hipFree(d_plain);
@@ -590,6 +597,13 @@ int vmt_server_run(vmt_server* s, const vmt_request* reqs, size_t n, vmt_result*
     }
     if (wall_s) *wall_s = wall;
     return err;
+}
+
+int vmt_server_set_watchdog(vmt_server* s, double seconds) {
+    if (!s) return server_fail(VMT_EINVAL, "null server");
+    if (!(seconds >= 0.0) || !std::isfinite(seconds)) return server_fail(VMT_EINVAL, "watchdog: 0 <= seconds < inf");
+    s->watchdog_s = seconds;
+    return VMT_OK;
 }
 
 int vmt_server_destroy(vmt_server* s) {

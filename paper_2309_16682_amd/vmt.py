@@ -86,6 +86,7 @@ def lib():
         "vmt_server_create": ([P, P, SZ, P, SZ, U64, I, U32, I, U64, IP], P),
         "vmt_server_run": ([P, P, SZ, P, I, ctypes.POINTER(ctypes.c_double)], I),
         "vmt_server_destroy": ([P], I),
+        "vmt_server_set_watchdog": ([P, ctypes.c_double], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -103,7 +104,7 @@ def exported_symbols() -> list:
         "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
         "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_check_poly",
         "vmt_check_stream", "vmt_shape_get", "vmt_shape_set", "vmt_autotune",
-        "vmt_server_create", "vmt_server_run", "vmt_server_destroy",
+        "vmt_server_create", "vmt_server_run", "vmt_server_destroy", "vmt_server_set_watchdog",
     ]
 
 
@@ -358,11 +359,19 @@ def vmt_server_run(server, requests, realtime=True):
         reqs[i] = vmt_request(float(t), int(st), int(kind), int(count), int(k), 0)
     res = (vmt_result * max(n, 1))()
     wall = ctypes.c_double(0.0)
-    _check(lib().vmt_server_run(server, reqs, n, res, 1 if realtime else 0, ctypes.byref(wall)))
+    code = lib().vmt_server_run(server, reqs, n, res, 1 if realtime else 0, ctypes.byref(wall))
     dt = np.dtype([("t_admit", "f8"), ("t_launch", "f8"), ("t_done", "f8"), ("out_offset", "u8"), ("status", "i4"),
                    ("launch", "i4")])
     out = np.frombuffer(bytes(res), dtype=dt, count=n).copy()
+    if code != 0:  # the results of a run that gave up are attached to the error
+        err = VmtError(code, lib().vmt_last_error().decode())
+        err.results = out
+        raise err
     return out, wall.value
+
+
+def vmt_server_set_watchdog(server, seconds):
+    return _check(lib().vmt_server_set_watchdog(server, float(seconds)))
 
 
 def vmt_server_destroy(server):

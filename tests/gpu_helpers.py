@@ -54,3 +54,26 @@ def pow2_poly(variant, k):
     while len(chain) <= k:
         chain.append(O.poly_sqrmod(chain[-1], golden_io.minpoly(variant)))
     return chain[k]
+
+
+def oracle_key_prefix(args):
+    """(variant, M, key, n) -> first n elements of the oracle V-stream from
+    init_by_array(key). Top-level so that a spawned worker process can run it:
+    it touches neither torch nor the GPU."""
+    variant, M, key, n = args
+    return oracle_stream(variant, M, key=[int(k) for k in key]).generate(int(n))
+
+
+def oracle_key_prefixes(variant, M, keys, ns, workers=8):
+    """oracle_key_prefix for many keys, on a pool of spawned CPU workers (the
+    oracle seeds each generator's M lanes by Horner jumps: a few tenths of a
+    second per generator)."""
+    import multiprocessing
+    import os
+
+    jobs = [(variant, M, tuple(int(x) for x in k), int(n)) for k, n in zip(keys, ns)]
+    workers = max(1, min(workers, os.cpu_count() or 1, len(jobs)))
+    if workers == 1:
+        return [oracle_key_prefix(j) for j in jobs]
+    with multiprocessing.get_context("spawn").Pool(workers) as pool:
+        return pool.map(oracle_key_prefix, jobs, chunksize=4)

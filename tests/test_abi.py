@@ -43,6 +43,12 @@ def test_host_only_context_and_error_paths():
         r = vmt.lib().vmt_init_genrand(ctx, 0, 1, 4, ctypes.c_void_p(256), None)
         assert r == vmt.VMT_EDEVICE
         assert b"host-only" in vmt.lib().vmt_last_error()
+        # a server needs a device; the server calls reject null handles
+        st = ctypes.c_int(0)
+        assert not vmt.lib().vmt_server_create(ctx, None, 0, None, 0, 0, 0, 1, 0, 0, ctypes.byref(st))
+        assert st.value == vmt.VMT_EDEVICE
+        assert vmt.lib().vmt_server_set_watchdog(None, 1.0) == vmt.VMT_EINVAL
+        assert vmt.lib().vmt_server_destroy(None) == vmt.VMT_EINVAL
     finally:
         vmt.vmt_ctx_destroy(ctx)
 

@@ -154,3 +154,67 @@ def test_server_rejects_mixed_states(ctx):
     with pytest.raises(vmt.VmtError) as e:
         vmt.vmt_server_create(ctx, [a, b], arena, 1 << 12, 1 << 12, vmt.VMT_OUT_U64)
     assert e.value.code == vmt.VMT_EINVAL
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_a_run_that_gives_up_reports_what_ran_and_the_server_recovers(ctx, mode):
+    # The give-up path, forced from the host: with a watchdog of 0 s the run gives up at its first check with work
+    # in flight. Every kernel still runs to its end; no request completes within the run.
+    n_states = 12
+    rng = np.random.default_rng(30 + mode)
+    reqs = []
+    for st in range(n_states):
+        for j in range(3):
+            if j == 1 and st % 3 == 0:
+                reqs.append((0.0, st, 1, 0, int(rng.integers(32, 80))))
+            else:
+                reqs.append((0.0, st, 0, int(rng.integers(1, 20000)), 0))
+    total = sum(((8 * r[3] + 255) // 256) * 256 for r in reqs) + 256
+    say(f"case serving give-up mode={mode} requests={len(reqs)}")
+    pool, states = make_states(ctx, n_states)
+    arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    srv = vmt.vmt_server_create(ctx, states, arena, total, total, vmt.VMT_OUT_U64, n_streams=2, mode=mode | 2)
+    try:
+        with pytest.raises(vmt.VmtError) as e:
+            vmt.vmt_server_set_watchdog(srv, -1.0)
+        assert e.value.code == vmt.VMT_EINVAL
+        vmt.vmt_server_set_watchdog(srv, 0.0)
+        with pytest.raises(vmt.VmtError) as e:
+            vmt.vmt_server_run(srv, reqs, realtime=False)
+        assert e.value.code == vmt.VMT_EBUSY
+        res1 = e.value.results
+        host1 = arena.cpu().numpy()
+        assert (res1["status"] == vmt.VMT_EBUSY).all()
+        ran = res1["launch"] >= 0
+        assert ran.any() and not ran.all()
+        # the same server, with the default bound again, serves what did not run
+        vmt.vmt_server_set_watchdog(srv, 30.0)
+        rest = [i for i in range(len(reqs)) if not ran[i]]
+        res2, _ = vmt.vmt_server_run(srv, [reqs[i] for i in rest], realtime=False)
+        host2 = arena.cpu().numpy()
+        assert (res2["status"] == 0).all()
+        tail = [torch.empty(1000, dtype=torch.int64, device="cuda") for _ in range(n_states)]
+        for st in range(n_states):
+            vmt.vmt_generate_u64(ctx, states[st], 1000, tail[st])
+        torch.cuda.synchronize()
+    finally:
+        vmt.vmt_server_destroy(srv)
+    where = {i: (host1, res1[i]) for i in range(len(reqs)) if ran[i]}
+    where.update({i: (host2, res2[j]) for j, i in enumerate(rest)})
+    gJ = golden_io.lane_poly(MT64, M)
+    for st in range(n_states):
+        idx = [i for i, r in enumerate(reqs) if r[1] == st]
+        # what ran of a state's requests is a prefix of them, in arrival order
+        flags = [bool(ran[i]) for i in idx]
+        assert flags == sorted(flags, reverse=True), (st, flags)
+        ref = O.VStream(MT64, M, O.seed_state(MT64, st + 1), gJ)
+        for i in idx:
+            host, r = where[i]
+            if reqs[i][2] == 1:
+                ref.jump(pow2_poly(MT64, reqs[i][4]))
+            else:
+                off, count = int(r["out_offset"]), reqs[i][3]
+                np.testing.assert_array_equal(host[off : off + 8 * count].view(np.uint64), ref.generate(count),
+                                              err_msg=f"request {i} state {st}")
+        np.testing.assert_array_equal(tail[st].cpu().numpy().view(np.uint64), ref.generate(1000),
+                                      err_msg=f"state {st} after both runs")
