@@ -343,19 +343,21 @@ int split_log2(const vmt_shape& sh, int variant, uint32_t M, uint64_t n, size_t 
     if (sh.split_log2) {
         v = (int)sh.split_log2;
     } else {
-        // Automatic. The jumps of a split call take about 0.7 ms (one lane jump per wavefront, all in
-        // parallel; up to 1024 lanes in the low-latency grouped form), so split only calls that would take
-        // a few times that in one launch: MT19937 from 32 MiB (one launch writes a few tens of GB/s),
-        // SFMT19937 from M MiB (its serial chains run at about 0.25 GB/s per lane). MT chunks: at most 1024
-        // lane jumps per call, at least 1 MiB each; SFMT chunks: 2^14 lane steps (its per-chunk rate is low,
-        // so many chunks pay off).
+        // Automatic. The jumps of a split call take 0.17 / 0.25 / 0.40 ms for up to 256 / 512 / 1024 MT lane
+        // jumps (each lane jump sliced over a workgroup), and one launch writes a few tens of GB/s, so MT calls
+        // split from 8 MiB, into at most 256 lane jumps up to 32 MiB, 512 up to 256 MiB and 1024 beyond, with
+        // chunks of at least 256 KiB. SFMT19937 splits from M MiB into chunks of 2^14 lane steps (its serial
+        // chains run at about 0.25 GB/s per lane, so many chunks pay off; beyond 1024 lane jumps the chunks
+        // share each lane's raw rows).
         if (vmt::is_sfmt(variant)) {
             if (n * eb < (uint64_t)M << 20) return -1;
             v = 14;
         } else {
-            if (n * eb < (32ull << 20)) return -1;
-            const uint64_t cmax = std::max<uint64_t>(1024 / M, 2);
-            v = std::max(ceil_log2(ceil_div(steps, cmax)), ceil_log2(ceil_div(1u << 20, M * epw * eb)));
+            const uint64_t bytes = n * eb;
+            if (bytes < (8ull << 20)) return -1;
+            const uint64_t lanes = bytes <= (32ull << 20) ? 256 : bytes <= (256ull << 20) ? 512 : 1024;
+            const uint64_t cmax = std::max<uint64_t>(lanes / M, 2);
+            v = std::max(ceil_log2(ceil_div(steps, cmax)), ceil_log2(ceil_div(256u << 10, M * epw * eb)));
         }
         while (ceil_div(steps, 1ull << v) > 4096) v++;
     }
@@ -440,7 +442,8 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
     e = hipMemcpyAsync(buf + off_bt, host.data(), off_ctr - off_bt, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = vmt::launch_replicate(d_state, buf, (uint32_t)sb, sbs, (uint32_t)(C - 1), stream);
-    if (e == hipSuccess) e = vmt::launch_jump(info.variant, M, d_jt, jt[0], (uint32_t)(C - 1), stream);
+    // copy 0 is chunk 0: it is not jumped and holds the window every other chunk starts from
+    if (e == hipSuccess) e = vmt::launch_split_jump(info.variant, M, buf, d_jt, jt[0], (uint32_t)(C - 1), stream);
     if (e == hipSuccess) {
         if (vmt::is_sfmt(info.variant)) {
             e = vmt::launch_batch_sfmt(info.variant, M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);

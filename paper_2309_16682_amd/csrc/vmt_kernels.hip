@@ -680,11 +680,18 @@ struct SfmtGen {
                 const uint32_t step = __builtin_amdgcn_readfirstlane(4u * M);
                 uint32_t o = 4u * (lane0 + q) + j;
                 OutT* op = out + o0 + o;
-                sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
-                    if (o < lim) *op = map(r);
-                    o += step;
-                    op += step;
-                });
+                if (lim == B) {  // a whole block: every output is in range, no per-step test
+                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
+                        gstore(op, map(r));
+                        op += step;
+                    });
+                } else {
+                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
+                        if (o < lim) gstore(op, map(r));
+                        o += step;
+                        op += step;
+                    });
+                }
             }
         }
         __syncthreads();
@@ -836,14 +843,23 @@ __device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const 
 // over the set bits e of the odd pattern q. One LDS read per non-zero group
 // instead of one per set coefficient: about 15/32 of the reads for a dense g.
 // rows: the eight derived rows (q = 1, 3, .., 15), `rstride` words apart.
+// Part `part` of `parts` takes the part-th contiguous slice of the block's
+// coefficient range (XOR is linear: the parts' sums add up to the block's).
 template <class W, int N>
 __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const W* rows, int rstride,
-                                                  const uint64_t* poly, int k, int b, int max_deg, int lane) {
+                                                  const uint64_t* poly, int k, int b, int max_deg, int lane,
+                                                  int part, int parts) {
     constexpr int S = (N + 63) / 64;
     int lo = b * N - k, hi = (b + 1) * N - k;  // coefficient range for this block
     if (lo < 0) lo = 0;
     if (hi > max_deg + 1) hi = max_deg + 1;
     if (lo >= hi) return;
+    if (parts > 1) {
+        const int len = hi - lo;
+        hi = lo + (len * (part + 1)) / parts;
+        lo = lo + (len * part) / parts;
+        if (lo >= hi) return;
+    }
     const int off0 = k - b * N + lane;
     auto next_group = [&](uint64_t& bits, int base) {  // row offset of the lowest non-zero group; clears it
         const int p = __builtin_ctzll(bits);  // lowest set coefficient: e0 = p mod 4 within its group
@@ -984,15 +1000,21 @@ constexpr int jump_row_words() {
     return GROUPED ? 8 * 2 * N : 2 * N;
 }
 
-template <class W, int N, int G, bool INIT, bool GROUPED>
+// WPL wavefronts per lane (jumps of few lanes): they share the lane's raw
+// row, each sums its slice of every block's coefficients, and the slices'
+// sums are XORed together at the end.
+template <class W, int N, int G, bool INIT, bool GROUPED, int WPL = 1>
 __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* poly, uint32_t lane_stride,
                         int max_deg, int k, const InitTask* init, W* buf) {
     constexpr int S = (N + 63) / 64;
     constexpr int ROWS = INIT ? 1 : G;
     constexpr int RW = jump_row_words<N, GROUPED>();  // words from one raw row to the next
+    static_assert(WPL == 1 || (GROUPED && !INIT && WPL * N <= RW), "sliced sums need the grouped jump's LDS");
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // lane of the group handled by this wave
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w = wave / WPL;             // lane of the group handled by this wave
+    const int part = wave - w * WPL;      // its slice of the coefficients
     state = uniform(state);
     poly = uniform(poly);
     k = (int)uniform((uint32_t)k);
@@ -1025,7 +1047,7 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
     const int last_b = (k + max_deg) / N;
     for (int b = 0; b <= last_b; ++b) {
         if (w < G) {
-            if constexpr (GROUPED) accumulate_block4<W, N>(acc, myrow, 2 * N, mypoly, k, b, max_deg, lane);
+            if constexpr (GROUPED) accumulate_block4<W, N>(acc, myrow, 2 * N, mypoly, k, b, max_deg, lane, part, WPL);
             else accumulate_block<W, N>(acc, myrow, mypoly, k, b, max_deg, lane);
         }
         if (b == last_b) break;
@@ -1043,6 +1065,22 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
         }
     }
     __syncthreads();
+    if constexpr (WPL > 1) {  // XOR the slices' sums and store rows of G contiguous words
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = lane + 64 * s;
+            if (j < N) buf[wave * N + j] = acc[s];
+        }
+        __syncthreads();
+        for (int i = tid; i < N * G; i += nthr) {
+            const int j = i / G, r = i - (i / G) * G;
+            W v = buf[(r * WPL) * N + j];
+#pragma unroll
+            for (int q = 1; q < WPL; ++q) v = xorw(v, buf[(r * WPL + q) * N + j]);
+            gwin[(size_t)j * M + lane0 + r] = v;
+        }
+        return;
+    }
     // stage as [j][lane] and store rows of G contiguous words
     if (w < G) {
 #pragma unroll
@@ -1080,8 +1118,8 @@ __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, Ini
     }
 }
 
-template <class W, int N, int G, bool GROUPED>
-__global__ __launch_bounds__(G * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
+template <class W, int N, int G, bool GROUPED, int WPL = 1>
+__global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
     __shared__ __attribute__((aligned(16))) W buf[jump_row_words<N, GROUPED>() * G];
     const uint32_t groups = M / G;
     const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
@@ -1089,8 +1127,73 @@ __global__ __launch_bounds__(G * 64) void jump_kernel(const JumpTask* tasks, Jum
     const StateHeader* h = reinterpret_cast<const StateHeader*>(task.state);
     const uint32_t per = sizeof(W) == 16 ? 4u : 1u;
     const int k = (int)(h->pos / (per * M));  // words of every lane already consumed
-    dephase<W, N, G, false, GROUPED>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k, nullptr,
-                                     buf);
+    dephase<W, N, G, false, GROUPED, WPL>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k,
+                                          nullptr, buf);
+}
+
+// Jumps of one state's copies by different distances (the chunks of a split
+// call): every copy starts from the same window, so lane t's raw sequence is
+// the same for all of them. One workgroup per (lane t, CPW copies): the raw
+// rows are regenerated and derived once, and wavefront w sums copy w's
+// polynomial over them (grouped form) and writes lane t of that copy. `src`
+// holds the common window and is not among the copies jumped.
+template <class W, int N, int CPW>
+__global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src, const JumpTask* tasks, uint32_t count,
+                                                              uint32_t M) {
+    constexpr int S = (N + 63) / 64;
+    constexpr int RW = jump_row_words<N, true>();
+    __shared__ __attribute__((aligned(16))) W buf[RW];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t t = blockIdx.x % M;  // lane of the state
+    const uint32_t first = (blockIdx.x / M) * CPW;
+    const uint32_t mine = first + w;
+    const bool active = mine < count;
+    const StateHeader* h = reinterpret_cast<const StateHeader*>(src);
+    const uint32_t per = sizeof(W) == 16 ? 4u : 1u;
+    const int k = (int)uniform((uint32_t)(h->pos / (per * M)));  // words of every lane already consumed
+    int max_deg = 0;  // the workgroup's blocks run to the highest degree among its copies' polynomials
+    for (uint32_t i = first; i < first + CPW && i < count; ++i) max_deg = max(max_deg, (int)tasks[i].max_deg);
+    max_deg = (int)uniform((uint32_t)max_deg);
+    uint8_t* dst = nullptr;
+    const uint64_t* poly = nullptr;
+    int my_deg = -1;
+    if (active) {
+        dst = uniform(tasks[mine].state);
+        poly = uniform(tasks[mine].poly);
+        my_deg = (int)uniform(tasks[mine].max_deg);
+    }
+    const W* gsrc = reinterpret_cast<const W*>(src + kHeaderBytes);
+    for (int j = tid; j < N; j += nthr) buf[j] = gsrc[(size_t)j * M + t];
+    __syncthreads();
+    twist_rows<W, N>(buf, buf + N, 1, RW, tid, nthr);
+    __syncthreads();
+    derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+    __syncthreads();
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    const int last_b = (k + max_deg) / N;
+    for (int b = 0; b <= last_b; ++b) {
+        if (active) accumulate_block4<W, N>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1);
+        if (b == last_b) break;
+        __syncthreads();
+        for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
+        __syncthreads();
+        twist_rows<W, N>(buf, buf + N, 1, RW, tid, nthr);
+        __syncthreads();
+        derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+        __syncthreads();
+    }
+    if (active) {
+        W* gdst = reinterpret_cast<W*>(dst + kHeaderBytes);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = lane + 64 * s;
+            if (j < N) gdst[(size_t)j * M + t] = acc[s];
+        }
+    }
 }
 
 __global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t count) {
@@ -1148,11 +1251,19 @@ static int lanes_per_group(uint32_t variant, uint32_t M) {
         default: { constexpr int GG = 16; __VA_ARGS__; break; } \
     }
 
-#define VMT_G2_SWITCH(G, ...)                                 \
-    switch (G) {                                              \
-        case 1: { constexpr int GG = 1; __VA_ARGS__; break; }  \
-        default: { constexpr int GG = 2; __VA_ARGS__; break; } \
+#define VMT_WPL_SWITCH(W, ...)                                \
+    switch (W) {                                              \
+        case 4: { constexpr int WW = 4; __VA_ARGS__; break; }  \
+        case 8: { constexpr int WW = 8; __VA_ARGS__; break; }  \
+        default: { constexpr int WW = 16; __VA_ARGS__; break; } \
     }
+#define VMT_CPW_SWITCH(C, ...)                                \
+    switch (C) {                                              \
+        case 4: { constexpr int CC = 4; __VA_ARGS__; break; }  \
+        case 8: { constexpr int CC = 8; __VA_ARGS__; break; }  \
+        default: { constexpr int CC = 16; __VA_ARGS__; break; } \
+    }
+constexpr uint64_t kSplitSharedLanes = 1024;  // up to this many lane jumps a split call jumps each lane alone
 #define VMT_G8_SWITCH(G, ...)                                 \
     switch (G) {                                              \
         case 1: { constexpr int GG = 1; __VA_ARGS__; break; }  \
@@ -1177,23 +1288,30 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
 
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
                        hipStream_t stream) {
-    // Up to 1024 lanes: grouped accumulation, two lanes per workgroup (80 KB of
-    // LDS); more: one coefficient at a time, eight lanes (four for SFMT) per
-    // workgroup in 40 KB, so that many more lanes share each compute unit.
-    const bool grouped = (uint64_t)count * M <= 1024;
-    int G = lanes_per_group(variant, M);
-    const int cap = grouped ? 2 : (is_sfmt(variant) ? 4 : 8);
-    if (G > cap) G = cap;
-    const dim3 grid(count * (M / G)), block(G * 64);
+    // Up to 1024 lanes: grouped accumulation, one lane per workgroup (40 KB of
+    // LDS) and WPL wavefronts per lane, each summing a slice of the
+    // coefficients: 16 for up to 256 lanes (one workgroup of 1024 threads per
+    // lane), 8 up to 512, 4 up to 1024 (four lanes' workgroups per compute
+    // unit). More lanes: one coefficient at a time, eight lanes (four for
+    // SFMT) per workgroup in 40 KB, so that many more lanes share each
+    // compute unit.
+    const uint64_t lanes = (uint64_t)count * M;
+    const bool grouped = lanes <= 1024;
     if (grouped) {
+        const int wpl = lanes <= 256 ? 16 : (lanes <= 512 ? 8 : 4);
+        const dim3 grid(count * M), block(wpl * 64);
         if (variant == kMT32) {
-            VMT_G2_SWITCH(G, jump_kernel<uint32_t, 624, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+            VMT_WPL_SWITCH(wpl, jump_kernel<uint32_t, 624, 1, true, WW><<<grid, block, 0, stream>>>(d_tasks, one, M))
         } else if (variant == kMT64) {
-            VMT_G2_SWITCH(G, jump_kernel<uint64_t, 312, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M))
+            VMT_WPL_SWITCH(wpl, jump_kernel<uint64_t, 312, 1, true, WW><<<grid, block, 0, stream>>>(d_tasks, one, M))
         } else {
-            VMT_SFMT_SWITCH(variant, VMT_G2_SWITCH(G, jump_kernel<uint4, NN, GG, true><<<grid, block, 0, stream>>>(d_tasks, one, M)))
+            VMT_SFMT_SWITCH(variant, VMT_WPL_SWITCH(wpl, jump_kernel<uint4, NN, 1, true, WW><<<grid, block, 0, stream>>>(d_tasks, one, M)))
         }
     } else {
+        int G = lanes_per_group(variant, M);
+        const int cap = is_sfmt(variant) ? 4 : 8;
+        if (G > cap) G = cap;
+        const dim3 grid(count * (M / G)), block(G * 64);
         if (variant == kMT32) {
             VMT_G8_SWITCH(G, jump_kernel<uint32_t, 624, GG, false><<<grid, block, 0, stream>>>(d_tasks, one, M))
         } else if (variant == kMT64) {
@@ -1208,6 +1326,29 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
     return hipGetLastError();
 }
 
+
+hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src, const JumpTask* d_tasks,
+                             const JumpTask& one, uint32_t count, hipStream_t stream) {
+    // Few lanes: each lane jump on its own, sliced over wavefronts. More: the
+    // copies share each lane's raw rows, CPW copies per workgroup (fewer when
+    // that leaves under 512 workgroups).
+    const uint64_t lanes = (uint64_t)count * M;
+    if (lanes <= kSplitSharedLanes) return launch_jump(variant, M, d_tasks, one, count, stream);
+    int cpw = 16;
+    while (cpw > 4 && (uint64_t)M * ((count + cpw - 1) / cpw) < 512) cpw /= 2;
+    const dim3 grid(M * ((count + cpw - 1) / cpw)), block(cpw * 64);
+    if (variant == kMT32) {
+        VMT_CPW_SWITCH(cpw, split_jump_kernel<uint32_t, 624, CC><<<grid, block, 0, stream>>>(d_src, d_tasks, count, M))
+    } else if (variant == kMT64) {
+        VMT_CPW_SWITCH(cpw, split_jump_kernel<uint64_t, 312, CC><<<grid, block, 0, stream>>>(d_src, d_tasks, count, M))
+    } else {
+        VMT_SFMT_SWITCH(variant, VMT_CPW_SWITCH(cpw, split_jump_kernel<uint4, NN, CC><<<grid, block, 0, stream>>>(d_src, d_tasks, count, M)))
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    finalize_jump_pos<<<(count + 255) / 256, 256, 0, stream>>>(d_tasks, one, count);
+    return hipGetLastError();
+}
 
 bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind) {
     if (lpw == 0 || lpw > 16 || (lpw & (lpw - 1)) || M % lpw) return false;

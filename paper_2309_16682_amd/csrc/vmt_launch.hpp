@@ -33,6 +33,12 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
                        hipStream_t stream);
 
+// Jump `count` copies of one state, each by its own polynomial (the chunks of
+// a split call), then fix their positions. d_src holds the window all copies
+// start from and is not one of them.
+hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src, const JumpTask* d_tasks,
+                             const JumpTask& one, uint32_t count, hipStream_t stream);
+
 // Generate `len` elements from one state into d_out with `lpw` lanes per
 // workgroup (lpw divides M; lpw == M uses one workgroup).
 hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state,

@@ -77,3 +77,26 @@ def oracle_key_prefixes(variant, M, keys, ns, workers=8):
         return [oracle_key_prefix(j) for j in jobs]
     with multiprocessing.get_context("spawn").Pool(workers) as pool:
         return pool.map(oracle_key_prefix, jobs, chunksize=4)
+
+
+def oracle_jumped_tail(args):
+    """(variant, M, seed, pre, k, n) -> the n elements of the oracle V-stream
+    from init_genrand(seed) that follow `pre` elements and a jump by 2^k."""
+    variant, M, seed, pre, k, n = args
+    ref = oracle_stream(variant, M, seed=seed)
+    ref.generate(pre)
+    ref.jump(pow2_poly(variant, k))
+    return ref.generate(n)
+
+
+def oracle_map(fn, jobs, workers=8):
+    """fn over jobs on a pool of spawned CPU workers (fn top-level in this
+    module; the workers touch neither torch nor the GPU)."""
+    import multiprocessing
+    import os
+
+    workers = max(1, min(workers, os.cpu_count() or 1, len(jobs)))
+    if workers == 1:
+        return [fn(j) for j in jobs]
+    with multiprocessing.get_context("spawn").Pool(workers) as pool:
+        return pool.map(fn, jobs, chunksize=2)

@@ -5,7 +5,8 @@ import pytest
 
 from oracle import pyoracle as O
 from tests import golden_io, stdpins
-from tests.gpu_helpers import pow2_poly, as_u, oracle_prefix, oracle_stream, out_dtype, say
+from tests.gpu_helpers import (as_u, oracle_jumped_tail, oracle_map, oracle_prefix, oracle_stream, out_dtype, pow2_poly,
+                               say)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -317,24 +318,24 @@ def test_state_window_after_init_is_first_twisted_block(ctx):
             np.testing.assert_array_equal(win[:, t], lane)
 
 
-@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4)])
-def test_jump_pow2_batch_matches_oracle(ctx, variant, M):
+# lanes per launch (count x M): up to 256, 512 and 1024 take the grouped jump with 16, 8 and 4 wavefronts per lane;
+# more take the per-coefficient form
+@pytest.mark.parametrize("variant,M,count", [(MT32, 16, 24), (MT64, 8, 24), (SFMT, 4, 24), (MT64, 8, 80),
+                                             (MT32, 16, 64), (SFMT, 4, 200), (MT64, 8, 132)])
+def test_jump_pow2_batch_matches_oracle(ctx, variant, M, count):
     # each state of a batch jumped by its own 2^k (repeated k, k = 0), from different positions
-    count = 24
     rng = np.random.default_rng(12)
     ks = [0, 1, 32, 32, 255, 256] + [int(x) for x in rng.integers(0, 300, count - 6)]
     pre = [int(x) for x in rng.integers(0, 3 * BLOCK[variant] * M, count)]
     say(f"case jump_pow2_batch variant={variant} M={M} count={count}")
+    refs = oracle_map(oracle_jumped_tail, [(variant, M, 900 + i, pre[i], ks[i], 1000) for i in range(count)])
     states = [new_init(ctx, variant, M, 900 + i) for i in range(count)]
     for st, p in zip(states, pre):
         gen(ctx, st, variant, p)
     vmt.vmt_jump_pow2_batch(ctx, states, ks)
     torch.cuda.synchronize()
     for i in range(count):
-        ref = oracle_stream(variant, M, seed=900 + i)
-        ref.generate(pre[i])
-        ref.jump(pow2_poly(variant, ks[i]))
-        np.testing.assert_array_equal(gen(ctx, states[i], variant, 1000), ref.generate(1000), err_msg=f"state {i}")
+        np.testing.assert_array_equal(gen(ctx, states[i], variant, 1000), refs[i], err_msg=f"state {i}")
 
 
 def test_jump_pow2_batch_with_more_distinct_k_than_the_distance_cache(ctx):

@@ -119,13 +119,15 @@ def test_batch_generate_and_split(ctx, variant):
         for i in range(count):
             np.testing.assert_array_equal(as_u(outs[i][: lens[i]].cpu(), variant), refs[i].generate(lens[i]),
                                           err_msg=f"rep {rep} task {i}")
-    # one call split by jump-ahead into chunks of 2^6 lane steps (many chunks), then lanes 2 per workgroup
-    for shape in ({"split_log2": 6, "lanes_per_wg": 4}, {"split_log2": 255, "lanes_per_wg": 2}):
+    # one call split by jump-ahead into chunks of 2^6 or 2^4 lane steps (many chunks; the last call makes more than
+    # 1024 lane jumps), then lanes 2 per workgroup
+    for shape in ({"split_log2": 6, "lanes_per_wg": 4}, {"split_log2": 4, "lanes_per_wg": 4},
+                  {"split_log2": 255, "lanes_per_wg": 2}):
         say(f"case sfmt-set split variant={variant} shape={shape}")
         vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, U32, **shape)
         try:
             st = new_init(ctx, variant, M, 31)
-            sizes = [5, 40 * B + 3, 7, 3 * B]
+            sizes = [5, 40 * B + 3, 7, 3 * B, 80001]
             got = np.concatenate([gen(ctx, st, variant, s) for s in sizes])
             np.testing.assert_array_equal(got, oracle_prefix(variant, M, 31, len(got)))
         finally:

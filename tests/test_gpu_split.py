@@ -70,6 +70,15 @@ CASES = [
     (SFMT, 4, vmt.VMT_OUT_F32, 10, 4.5, 2497),
     (SFMT, 64, vmt.VMT_OUT_U32, 6, 7.7, 333),
     (SFMT, 1, vmt.VMT_OUT_U32, 12, 3.3, 2),
+    # more than 1024 lane jumps: the copies share each lane's raw rows, 4 / 8 / 16 copies per workgroup
+    (MT32, 16, vmt.VMT_OUT_U32, 4, 100.5, 7),
+    (MT32, 16, vmt.VMT_OUT_U32, 4, 600.2, 3000),
+    (MT32, 1, vmt.VMT_OUT_U32, 4, 1500.5, 100),
+    (MT64, 8, vmt.VMT_OUT_F64, 4, 150.3, 311),
+    (MT64, 4, vmt.VMT_OUT_U64, 5, 1100.9, 2),
+    (SFMT, 4, vmt.VMT_OUT_U32, 4, 300.7, 5),
+    (SFMT, 64, vmt.VMT_OUT_F32, 4, 20.2, 1000),
+    (SFMT, 2, vmt.VMT_OUT_U32, 4, 4200.1, 9),
 ]
 
 
@@ -95,10 +104,12 @@ def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre):
     np.testing.assert_array_equal(run(ctx, st, variant, native(variant), tail), ref.generate(tail))
 
 
-@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4), (SFMT, 64)])
-def test_automatic_split_of_a_long_call(ctx, variant, M):
-    # lengths the library splits by itself (40 MiB for MT19937, 6 MiB for SFMT19937), from a mid-block position
-    n = ((40 << 20) if variant != SFMT else (6 << 20)) // (8 if variant == MT64 else 4) + 12345
+@pytest.mark.parametrize("variant,M,mib", [(MT32, 16, 10), (MT32, 16, 40), (MT64, 8, 10), (MT64, 8, 40), (SFMT, 4, 6),
+                                           (SFMT, 64, 6), (MT32, 16, 300)])
+def test_automatic_split_of_a_long_call(ctx, variant, M, mib):
+    # lengths the library splits by itself (MT19937 from 8 MiB into up to 256, 512 or 1024 lane jumps by size;
+    # SFMT19937 from M MiB), from a mid-block position
+    n = (mib << 20) // (8 if variant == MT64 else 4) + 12345
     say(f"case auto split variant={variant} M={M} n={n}")
     seed = 77
     st = vmt.new_state(variant, M)
