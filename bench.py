@@ -47,10 +47,10 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "76833bc923b9c4b560b50abb8afa5a77b9dbe3296cee55e26cb98c6ff9c934a8",
+    "kernel_fingerprint": "f07c06ae5ab0f44dc6ec3a7b064544c0b3717ede2834985a615f18e8c1619809",
     "shapes": {
-        (512, 16, 2): (878112683, 96283548149),
-        (512, 8, 2): (878247979, 96283547797),
+        (512, 16, 2): (878122837, 96283547893),
+        (512, 8, 2): (878132907, 96283547808),
     },
 }
 

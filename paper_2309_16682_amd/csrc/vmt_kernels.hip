@@ -1331,9 +1331,12 @@ hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src,
                              const JumpTask& one, uint32_t count, hipStream_t stream) {
     // Few lanes: each lane jump on its own, sliced over wavefronts. More: the
     // copies share each lane's raw rows, CPW copies per workgroup (fewer when
-    // that leaves under 512 workgroups).
+    // that leaves under 512 workgroups). States of fewer than 16 words (SFMT607,
+    // SFMT1279) keep a row per lane jump: their blocks are so short that the
+    // barriers of a wide workgroup cost more than regenerating the rows.
     const uint64_t lanes = (uint64_t)count * M;
-    if (lanes <= kSplitSharedLanes) return launch_jump(variant, M, d_tasks, one, count, stream);
+    if (lanes <= kSplitSharedLanes || words_per_lane(variant) < 16)
+        return launch_jump(variant, M, d_tasks, one, count, stream);
     int cpw = 16;
     while (cpw > 4 && (uint64_t)M * ((count + cpw - 1) / cpw) < 512) cpw /= 2;
     const dim3 grid(M * ((count + cpw - 1) / cpw)), block(cpw * 64);
