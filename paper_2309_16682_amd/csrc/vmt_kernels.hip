@@ -845,7 +845,10 @@ __device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const 
 // rows: the eight derived rows (q = 1, 3, .., 15), `rstride` words apart.
 // Part `part` of `parts` takes the part-th contiguous slice of the block's
 // coefficient range (XOR is linear: the parts' sums add up to the block's).
-template <class W, int N>
+// PADDED: the buffer extends jump_pad_words<N>() words past the last derived
+// row, so the reads of the last partial wavefront row need no range test
+// (lanes past the window read words they never store).
+template <class W, int N, bool PADDED = false>
 __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const W* rows, int rstride,
                                                   const uint64_t* poly, int k, int b, int max_deg, int lane,
                                                   int part, int parts) {
@@ -878,11 +881,13 @@ __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const
             const W* sa = rows + off0 + next_group(bits, base);
             W va[S], vb[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s) va[s] = (s < S - 1 || lane + 64 * s < N) ? sa[64 * s] : zero_w<W>();
+            for (int s = 0; s < S; ++s)
+                va[s] = (PADDED || s < S - 1 || lane + 64 * s < N) ? sa[64 * s] : zero_w<W>();
             if (bits) {
                 const W* sb = rows + off0 + next_group(bits, base);
 #pragma unroll
-                for (int s = 0; s < S; ++s) vb[s] = (s < S - 1 || lane + 64 * s < N) ? sb[64 * s] : zero_w<W>();
+                for (int s = 0; s < S; ++s)
+                    vb[s] = (PADDED || s < S - 1 || lane + 64 * s < N) ? sb[64 * s] : zero_w<W>();
 #pragma unroll
                 for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], xorw(va[s], vb[s]));
             } else {
@@ -999,6 +1004,18 @@ template <int N, bool GROUPED>
 constexpr int jump_row_words() {
     return GROUPED ? 8 * 2 * N : 2 * N;
 }
+// Words past the last derived row that the unguarded reads of a padded
+// buffer can reach: a wavefront row reads 64 * ceil(N / 64) words from a
+// start below N in the last row.
+template <int N>
+constexpr int jump_pad_words() {
+    return 64 * ((N + 63) / 64) - N;
+}
+// uint64 polynomial words staged in LDS by a sliced jump, in units of W
+template <class W>
+constexpr int jump_poly_stage_words() {
+    return (int)((kPolyWords * sizeof(uint64_t) + sizeof(W) - 1) / sizeof(W));
+}
 
 // WPL wavefronts per lane (jumps of few lanes): they share the lane's raw
 // row, each sums its slice of every block's coefficients, and the slices'
@@ -1009,7 +1026,13 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
     constexpr int S = (N + 63) / 64;
     constexpr int ROWS = INIT ? 1 : G;
     constexpr int RW = jump_row_words<N, GROUPED>();  // words from one raw row to the next
-    static_assert(WPL == 1 || (GROUPED && !INIT && WPL * N <= RW), "sliced sums need the grouped jump's LDS");
+    static_assert(WPL == 1 || (GROUPED && !INIT && G == 1 && WPL * N <= RW), "sliced sums need the grouped jump's LDS");
+    // Sliced jumps: the buffer is padded (unguarded reads), and with 8 or more
+    // wavefronts the lane's polynomial is staged in LDS after the pad, so that
+    // each block's first coefficient word is an LDS read rather than a global
+    // one on the critical path.
+    constexpr bool PADDED = WPL > 1;
+    constexpr bool STAGED = WPL >= 8;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1031,6 +1054,11 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
             buf[r * RW + j] = gwin[(size_t)j * M + lane0 + r];
         }
     }
+    uint64_t* spoly = reinterpret_cast<uint64_t*>(buf + RW * G + jump_pad_words<N>());
+    if constexpr (STAGED) {
+        const uint64_t* src = poly + (size_t)lane_stride * lane0;
+        for (int i = tid; i <= (max_deg >> 6); i += nthr) spoly[i] = src[i];
+    }
     __syncthreads();
     twist_rows<W, N>(buf, buf + N, ROWS, RW, tid, nthr);
     __syncthreads();
@@ -1042,12 +1070,13 @@ __device__ void dephase(uint8_t* state, uint32_t M, uint32_t g, const uint64_t* 
     W acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
-    const uint64_t* mypoly = poly + (size_t)lane_stride * (lane0 + w);
+    const uint64_t* mypoly = STAGED ? spoly : poly + (size_t)lane_stride * (lane0 + w);
     const W* myrow = buf + (INIT ? 0 : w * RW);
     const int last_b = (k + max_deg) / N;
     for (int b = 0; b <= last_b; ++b) {
         if (w < G) {
-            if constexpr (GROUPED) accumulate_block4<W, N>(acc, myrow, 2 * N, mypoly, k, b, max_deg, lane, part, WPL);
+            if constexpr (GROUPED)
+                accumulate_block4<W, N, PADDED>(acc, myrow, 2 * N, mypoly, k, b, max_deg, lane, part, WPL);
             else accumulate_block<W, N>(acc, myrow, mypoly, k, b, max_deg, lane);
         }
         if (b == last_b) break;
@@ -1120,7 +1149,8 @@ __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, Ini
 
 template <class W, int N, int G, bool GROUPED, int WPL = 1>
 __global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
-    __shared__ __attribute__((aligned(16))) W buf[jump_row_words<N, GROUPED>() * G];
+    constexpr int EXTRA = (WPL > 1 ? jump_pad_words<N>() : 0) + (WPL >= 8 ? jump_poly_stage_words<W>() : 0);
+    __shared__ __attribute__((aligned(16))) W buf[jump_row_words<N, GROUPED>() * G + EXTRA];
     const uint32_t groups = M / G;
     const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
     const JumpTask task = tasks ? tasks[ti] : one;
@@ -1142,7 +1172,7 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
                                                               uint32_t M) {
     constexpr int S = (N + 63) / 64;
     constexpr int RW = jump_row_words<N, true>();
-    __shared__ __attribute__((aligned(16))) W buf[RW];
+    __shared__ __attribute__((aligned(16))) W buf[RW + jump_pad_words<N>()];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
     const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1176,7 +1206,7 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
     for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
     const int last_b = (k + max_deg) / N;
     for (int b = 0; b <= last_b; ++b) {
-        if (active) accumulate_block4<W, N>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1);
+        if (active) accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1);
         if (b == last_b) break;
         __syncthreads();
         for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
