@@ -47,10 +47,10 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "f07c06ae5ab0f44dc6ec3a7b064544c0b3717ede2834985a615f18e8c1619809",
+    "kernel_fingerprint": "929697397a0d34fc37fd17f2b7a7264049932574ea26ceb0d3d0ce1a4e69f382",
     "shapes": {
-        (512, 16, 2): (878122837, 96283547893),
-        (512, 8, 2): (878132907, 96283547808),
+        (512, 16, 2): (878149205, 96283548000),
+        (512, 8, 2): (878205056, 96283547861),
     },
 }
 
