@@ -47,10 +47,10 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "929697397a0d34fc37fd17f2b7a7264049932574ea26ceb0d3d0ce1a4e69f382",
+    "kernel_fingerprint": "3bf0369786e017762cc375824278fb3de420dc0b0830c39c717004af9ba20f28",
     "shapes": {
-        (512, 16, 2): (878149205, 96283548000),
-        (512, 8, 2): (878205056, 96283547861),
+        (512, 16, 2): (877959765, 96283547979),
+        (512, 8, 2): (878104149, 96283547840),
     },
 }
 

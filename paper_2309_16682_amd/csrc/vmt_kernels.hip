@@ -864,27 +864,35 @@ __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const
         if (lo >= hi) return;
     }
     const int off0 = k - b * N + lane;
-    auto next_group = [&](uint64_t& bits, int base) {  // row offset of the lowest non-zero group; clears it
-        const int p = __builtin_ctzll(bits);  // lowest set coefficient: e0 = p mod 4 within its group
-        const int u0 = p & ~3;
-        const int q = (int)((bits >> u0) & 0xF) >> (p - u0);  // odd pattern from e0 up
-        bits &= ~(0xFull << u0);
-        return (q >> 1) * rstride + base + p;
-    };
+    // The 16 groups of a 64-coefficient word are decoded side by side, lane u
+    // taking group u (lanes 16 .. 63 repeat them): its pattern, lowest set bit
+    // e0 and row offset. The scalar loop then walks the mask of non-zero groups
+    // and reads each offset from its lane.
+    const int u = lane & 15;
     for (int wi = lo >> 6; wi <= (hi - 1) >> 6; ++wi) {
-        uint64_t bits = uniform(poly[wi]);  // scalar: the loop over coefficients runs on the scalar unit
+        uint64_t bits = uniform(poly[wi]);
         const int base = wi * 64;
         if (base < lo) bits &= ~0ull << (lo - base);
         if (base + 64 > hi) bits &= (hi - base >= 64) ? ~0ull : ((1ull << (hi - base)) - 1);
-        while (bits) {
+        if (!bits) continue;
+        const uint32_t pat = (uint32_t)(bits >> (4 * u)) & 0xFu;
+        const int e0 = __builtin_ctz(pat | 0x10u);
+        const int grp_off = (int)((pat >> e0) >> 1) * rstride + 4 * u + e0;  // odd pattern from e0 up
+        uint64_t live = __ballot(pat != 0) & 0xFFFFull;  // non-zero groups (lanes 0 .. 15)
+        auto next_group = [&]() {  // row offset of the lowest remaining group; clears it
+            const int g = __builtin_ctzll(live);
+            live &= live - 1;
+            return base + __builtin_amdgcn_readlane(grp_off, g);
+        };
+        while (live) {
             // two groups per round: the second group's reads are in flight with the first's
-            const W* sa = rows + off0 + next_group(bits, base);
+            const W* sa = rows + off0 + next_group();
             W va[S], vb[S];
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 va[s] = (PADDED || s < S - 1 || lane + 64 * s < N) ? sa[64 * s] : zero_w<W>();
-            if (bits) {
-                const W* sb = rows + off0 + next_group(bits, base);
+            if (live) {
+                const W* sb = rows + off0 + next_group();
 #pragma unroll
                 for (int s = 0; s < S; ++s)
                     vb[s] = (PADDED || s < S - 1 || lane + 64 * s < N) ? sb[64 * s] : zero_w<W>();
