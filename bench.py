@@ -47,10 +47,10 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "3bf0369786e017762cc375824278fb3de420dc0b0830c39c717004af9ba20f28",
+    "kernel_fingerprint": "6a77ae598ba586d6daf9e0aff9b050cd4de668d1ab0ceb3be31e2542d3970261",
     "shapes": {
-        (512, 16, 2): (877959765, 96283547979),
-        (512, 8, 2): (878104149, 96283547840),
+        (512, 16, 2): (878041515, 96283548064),
+        (512, 8, 2): (878127275, 96283547808),
     },
 }
 

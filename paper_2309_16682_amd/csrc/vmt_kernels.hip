@@ -33,7 +33,8 @@
 // derived rows (accumulate_block4).
 //
 // SFMT19937's recurrence is serial along each lane; a quad of threads shares
-// a lane, one 32-bit sub-word each (sfmt_block_quad).
+// a lane, one 32-bit sub-word each (sfmt_block_quad), laid out 4 threads apart
+// within a row of 16 (sfmt_quad_thread).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -200,11 +201,22 @@ __device__ __forceinline__ uint64_t temper(uint64_t y) {
 // stored: the critical path of a step is the recurrence itself (the shift of
 // w_{k+N-1} and an XOR). (A chain that loads each operand right before use
 // waits for an LDS round trip per step, ~200 cycles.)
-__device__ __forceinline__ uint32_t quad_next(uint32_t x) {  // value of quad thread j + 1 (j = 3: own)
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xF9, 0xF, 0xF, false);
+// Quad layout: sub-word j of lane group q is thread 16 (q / 4) + 4 j + q % 4,
+// so the four sub-words of a lane sit 4 threads apart in one row of 16. The
+// neighbour's sub-word is then a row shift by 4 (DPP row_shl / row_shr), and
+// the shift supplies the zero that sub-words 3 and 0 need at the row's ends
+// (the source lane is outside the row), with no separate mask.
+struct QuadThread {
+    int q, j;
+};
+__device__ __forceinline__ QuadThread sfmt_quad_thread(int tid) {
+    return QuadThread{((tid >> 4) << 2) | (tid & 3), (tid >> 2) & 3};
 }
-__device__ __forceinline__ uint32_t quad_prev(uint32_t x) {  // value of quad thread j - 1 (j = 0: own)
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x90, 0xF, 0xF, false);
+__device__ __forceinline__ uint32_t quad_next(uint32_t x) {  // sub-word j + 1 of the lane (j = 3: zero)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t quad_prev(uint32_t x) {  // sub-word j - 1 of the lane (j = 0: zero)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);
 }
 
 constexpr int kPrefetch = 8;  // steps between an operand load and its use
@@ -220,8 +232,6 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
     constexpr int PD = kPrefetch < N ? kPrefetch : N;
     // the mask K of eq. (sfmt_params), sub-word j
     const uint32_t K = j == 0 ? P::K0 : j == 1 ? P::K1 : j == 2 ? P::K2 : P::K3;
-    const uint32_t lo_mask = j ? ~0u : 0u;  // sub-word 0 has no lower neighbour
-    const uint32_t hi_mask = j < 3 ? ~0u : 0u;  // sub-word 3 has no upper neighbour
     // all indices below are compile-time constants after unrolling: the arrays are registers,
     // and only the live window of each (PD loads ahead, N - MM new words back) occupies any
     uint32_t pa[N], pb[N], nw[N];
@@ -232,7 +242,7 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
     }
     // cn, dn: the upper neighbour's sub-word of c and d, zero for sub-word 3
     uint32_t c = src[(N - 2) * ws + j], d = src[(N - 1) * ws + j];
-    uint32_t cn = quad_next(c) & hi_mask, dn = quad_next(d) & hi_mask;
+    uint32_t cn = quad_next(c), dn = quad_next(d);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         if (k + PD < N) {  // operands of step k + PD: old words, not yet overwritten
@@ -241,7 +251,7 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
         }
         const uint32_t ak = pa[k], bk = k + MM < N ? pb[k] : nw[k + MM - N];
         // (a <<< SL2) and (c >>> SR2) on this sub-word: funnel shifts with the neighbour's sub-word
-        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak) & lo_mask, 32 - P::SL2);
+        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak), 32 - P::SL2);
         const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, P::SR2);
         uint32_t r = xor3(ak, al, cr);
         r = xor_and(r, bk >> P::SR1, K);
@@ -252,7 +262,7 @@ __device__ __forceinline__ void sfmt_block_quad(const uint32_t* src, uint32_t* d
         c = d;
         cn = dn;
         d = r;
-        dn = quad_next(r) & hi_mask;
+        dn = quad_next(r);
     }
 }
 
@@ -668,7 +678,8 @@ struct SfmtGen {
         }
         __syncthreads();
         // full blocks: lane group q of the workgroup, quad thread j owns sub-word j
-        const int q = tid >> 2, j = tid & 3;
+        const QuadThread qt = sfmt_quad_thread(tid);
+        const int q = qt.q, j = qt.j;
         uint32_t* w32 = reinterpret_cast<uint32_t*>(win);
         if (q < LPW) {
             for (uint64_t b = 0; b < nblocks; ++b) {
@@ -796,7 +807,8 @@ __device__ void raw_twist_rows(const typename P::W* src, typename P::W* dst, int
 
 template <int N>
 __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int stride, int tid) {
-    const int row = tid >> 2, j = tid & 3;  // one quad of threads per row
+    const QuadThread qt = sfmt_quad_thread(tid);  // one quad of threads per row
+    const int row = qt.q, j = qt.j;
     if (row >= rows) return;
     sfmt_block_quad<N>(reinterpret_cast<const uint32_t*>(src + row * stride), reinterpret_cast<uint32_t*>(dst + row * stride),
                        4, j, [](int, uint32_t) {});
