@@ -51,6 +51,9 @@ COUNTERS = {
     "shapes": {
         (512, 16, 2): (878041515, 96283548064),
         (512, 8, 2): (878127275, 96283547808),
+        (256, 16, 2): (878075563, 96283547808),
+        (256, 8, 3): (878396587, 96283564320),
+        (960, 16, 2): (878025387, 96283549003),
     },
 }
 
