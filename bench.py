@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "6a77ae598ba586d6daf9e0aff9b050cd4de668d1ab0ceb3be31e2542d3970261",
+    "kernel_fingerprint": "aa7fd6d81b5773298c74a82fd4d973c6fa88cba5b7c75266c6a1296d81e1ea66",
     "shapes": {
-        (512, 16, 2): (878041515, 96283548064),
-        (512, 8, 2): (878127275, 96283547808),
-        (256, 16, 2): (878075563, 96283547808),
-        (256, 8, 3): (878396587, 96283564320),
-        (960, 16, 2): (878025387, 96283549003),
+        (512, 16, 2): (877941333, 96283547893),
+        (512, 8, 2): (878038699, 96283547797),
+        (256, 16, 2): (878112981, 96283547797),
+        (256, 8, 3): (878321408, 96283564288),
+        (960, 16, 2): (878084992, 96283549440),
     },
 }
 

@@ -404,7 +404,7 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
 }
 
 int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64_t n, uint8_t* d_out, int out_kind,
-                   int v, hipStream_t stream) {
+                   int v, uint32_t lpw, hipStream_t stream) {
     const uint32_t M = info.M;
     const uint64_t epw = vmt::is_sfmt(info.variant) ? 4 : 1;
     const uint64_t E = (1ull << v) * M * epw;  // elements per chunk
@@ -447,6 +447,8 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     if (e == hipSuccess) {
         if (vmt::is_sfmt(info.variant)) {
             e = vmt::launch_batch_sfmt(info.variant, M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
+        } else if (lpw < M) {  // each chunk's lanes spread over M / lpw workgroups
+            e = vmt::launch_batch_gen_mt(info.variant, M, lpw, out_kind, d_bt, (uint32_t)C, stream);
         } else {
             vmt::BatchShape shape;
             vmt::ctx_batch_shape(ctx, info.variant, M, out_kind, &shape);
@@ -482,9 +484,9 @@ int generate(vmt_ctx* ctx, void* d_state, size_t n, void* d_out, int out_kind, h
     if (!vmt::generate_supported(info.variant, info.M, lpw, out_kind))
         return fail(VMT_EVARIANT, "output kind %d not defined for variant %d", out_kind, info.variant);
     const int v = split_log2(sh, info.variant, info.M, n, out_elem_bytes(out_kind), out_kind);
-    if (v >= 0)
+    if (v >= 0)  // a split call runs its MT chunks by lane groups only with a tuned lanes-per-workgroup below M
         return generate_split(ctx, info, static_cast<uint8_t*>(d_state), n, static_cast<uint8_t*>(d_out), out_kind, v,
-                              stream);
+                              sh.lanes_per_wg ? sh.lanes_per_wg : info.M, stream);
     hipError_t e = vmt::launch_generate(info.variant, info.M, lpw, out_kind, static_cast<uint8_t*>(d_state), d_out,
                                         n, stream);
     if (e != hipSuccess) return hip_fail(e, "generate launch");

@@ -735,6 +735,18 @@ __global__ __launch_bounds__(64) void batch_sfmt_kernel(const BatchTask* tasks) 
     G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
 }
 
+// Batched MT generation by lane groups (the chunks of a split call):
+// workgroup (g, t) runs lane group g of task t with the single-state code, so
+// a chunk's M lanes spread over M / LPW workgroups. With several groups per
+// state the positions are fixed afterwards (finalize_batch_pos).
+template <class P, int LPW, int OUT>
+__global__ __launch_bounds__((mt_threads<P, LPW>())) void batch_gen_mt_kernel(const BatchTask* tasks) {
+    using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
+    __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LPW];
+    const BatchTask task = tasks[blockIdx.y];
+    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
+}
+
 // Copy whole states (header and window; `bytes` a multiple of 16): task y
 // copies tasks[y].src to tasks[y].dst.
 __global__ void copy_states(const CopyTask* tasks, uint32_t bytes) {
@@ -1532,6 +1544,31 @@ hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out
         VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_tasks)))
     } else {
         VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_tasks)))
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || lpw == M) return e;
+    finalize_batch_pos<<<(count + 255) / 256, 256, 0, stream>>>(d_tasks, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
+                               uint32_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const dim3 grid(M / lpw, count);
+    if (variant == kMT32) {
+        if (out_kind == kOutU32) {
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks))
+        } else {
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks))
+        }
+    } else {
+        if (out_kind == kOutU64) {
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+        } else if (out_kind == kOutF64) {
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+        } else {
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || lpw == M) return e;

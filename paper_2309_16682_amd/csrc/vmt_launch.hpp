@@ -75,6 +75,12 @@ hipError_t reset_counters(uint32_t* d_counter, hipStream_t stream);
 hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape, const BatchTask* d_tasks,
                         uint32_t count, uint32_t* d_counter, hipStream_t stream);
 
+// MT19937-32/-64 tasks by lane groups: M / lpw workgroups per task, each
+// running lpw lanes (lpw a power of two dividing M, at most 16); positions
+// are maintained like launch_generate's.
+hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
+                               uint32_t count, hipStream_t stream);
+
 // Batched SFMT generation (one lane group of lpw lanes per workgroup, tasks
 // of one M); positions are maintained like launch_generate's.
 hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,

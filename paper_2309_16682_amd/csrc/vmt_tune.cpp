@@ -133,15 +133,22 @@ int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind
             shapes.push_back(sh);
         }
         const bool can_split = vmt::is_sfmt(variant) || vmt::batch_supported(variant, M, out_kind);
+        // MT chunks run whole (lanes_per_wg = M, the persistent batch kernel) or by lane groups of 1 .. M/2
+        // lanes; SFMT chunks always run 16 lanes per workgroup (or M if fewer)
+        std::vector<uint32_t> split_lpw{M < 16 ? M : 16};
+        for (uint32_t lpw = 1; !vmt::is_sfmt(variant) && lpw < M && lpw <= 16; lpw *= 2)
+            if (vmt::generate_supported(variant, M, lpw, out_kind)) split_lpw.push_back(lpw);
         for (uint32_t v = 4; can_split && v <= 40; v++) {
             const uint64_t chunks = (steps + (1ull << v) - 1) >> v;
             if (chunks < 2) break;
             if (chunks > 4096 || (1ull << v) * M * epw * eb < (16u << 10)) continue;
-            vmt_shape sh{};
-            sh.lanes_per_wg = M < 16 ? M : 16;
-            sh.store_bytes = 16;
-            sh.split_log2 = v;
-            shapes.push_back(sh);
+            for (uint32_t lpw : split_lpw) {
+                vmt_shape sh{};
+                sh.lanes_per_wg = lpw;
+                sh.store_bytes = 16;
+                sh.split_log2 = v;
+                shapes.push_back(sh);
+            }
         }
         for (vmt_shape sh : shapes) {
             st = vmt_shape_set(ctx, family, variant, M, out_kind, &sh);

@@ -82,10 +82,24 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant,M,kind,v,chunks,pre", CASES)
-def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre):
+# MT chunks by lane groups (lanes per workgroup below M): variant, M, kind, split_log2, chunks, start, lanes per workgroup
+LANE_GROUP_CASES = [
+    (MT32, 16, vmt.VMT_OUT_U32, 6, 9.3, 4321, 1),
+    (MT32, 16, vmt.VMT_OUT_F32, 5, 33.7, 17, 4),
+    (MT32, 8, vmt.VMT_OUT_U32, 7, 12.2, 0, 2),
+    (MT32, 2, vmt.VMT_OUT_U32, 9, 5.01, 623, 1),
+    (MT64, 8, vmt.VMT_OUT_U64, 5, 20.7, 1, 1),
+    (MT64, 8, vmt.VMT_OUT_F64, 6, 11.1, 2495, 4),
+    (MT64, 16, vmt.VMT_OUT_F32, 7, 6.6, 100, 8),
+    (MT32, 16, vmt.VMT_OUT_U32, 4, 100.5, 7, 2),  # more than 1024 lane jumps as well
+]
+
+
+@pytest.mark.parametrize("variant,M,kind,v,chunks,pre,lpw",
+                         [c + (min(c[1], 16),) for c in CASES] + LANE_GROUP_CASES)
+def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre, lpw):
     n = int(chunks * (1 << v) * M * EPW[variant])
-    say(f"case split variant={variant} M={M} kind={kind} v={v} n={n} pre={pre}")
+    say(f"case split variant={variant} M={M} kind={kind} v={v} n={n} pre={pre} lanes_per_wg={lpw}")
     seed = 1000 + v
     st = vmt.new_state(variant, M)
     vmt.vmt_init_genrand(ctx, variant, seed, M, st)
@@ -93,7 +107,7 @@ def test_split_call_equals_oracle_stream(ctx, variant, M, kind, v, chunks, pre):
     if pre:
         run(ctx, st, variant, native(variant), pre)  # any start position, single launch
         ref.generate(pre)
-    vmt.vmt_shape_set(ctx, GEN, variant, M, kind, lanes_per_wg=min(M, 16), split_log2=v)
+    vmt.vmt_shape_set(ctx, GEN, variant, M, kind, lanes_per_wg=lpw, split_log2=v)
     try:
         got = run(ctx, st, variant, kind, n)
     finally:
