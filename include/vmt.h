@@ -327,7 +327,10 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
  * the state itself, all in one batched launch, so the state ends where the
  * call ends (on a block grid shifted by the jump). split_log2 = 0 lets the
  * library decide from the call size, 255 never splits, 4..40 fixes the chunk.
- * MT19937-32/-64 split only for M <= 16. Splitting needs the jump tables of the
+ * MT19937-32/-64 split only for M <= 16; their chunks run one workgroup per
+ * chunk when lanes_per_wg is 0 or M, and by lane groups (M / lanes_per_wg
+ * workgroups per chunk) when lanes_per_wg is below M; SFMT chunks run
+ * min(M, 16) lanes per workgroup. Splitting needs the jump tables of the
  * chunk offsets (computed on the host once per chunk length) and a scratch
  * copy of the state per chunk (stream-ordered allocation). */
 enum { VMT_FAMILY_GENERATE = 0, VMT_FAMILY_BATCH = 1 };
