@@ -255,7 +255,7 @@ def single_streams(ctx, torch, args, only=None) -> dict:
             lpw = b.lanes_per_wg
             split = b.split_log2
             log(f"{name} autotune: " + ", ".join(
-                f"{'lpw=%d' % t.lanes_per_wg if t.split_log2 == 255 else 'split=2^%d' % t.split_log2}: "
+                f"{'lpw=%d' % t.lanes_per_wg if t.split_log2 == 255 else 'split=2^%d/lpw=%d' % (t.split_log2, t.lanes_per_wg)}: "
                 f"{t.gbps:.1f}" for t in tried))
         st = vmt.new_state(variant, M)
         vmt.vmt_init_genrand(ctx, variant, seed, M, st)
