@@ -1179,9 +1179,83 @@ __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, Ini
     }
 }
 
+// One lane's jump by a workgroup of 16 wavefronts, pipelined over two LDS
+// row sets (raw window of two blocks and its derived rows, padded): while
+// wavefronts 1 .. 15 sum their slices of block b's coefficients from one set,
+// wavefront 0 builds block b + 1's window in the other (its lower half is the
+// current upper half, its upper half the next twist, then the derived rows),
+// so a block costs one barrier. Wavefront 0 works alone on its set: its LDS
+// writes and later reads of them are ordered by a wavefront-scope fence.
+template <class W, int N>
+__device__ void jump_pipelined(uint8_t* state, uint32_t M, uint32_t lane0, const uint64_t* poly, int max_deg, int k,
+                               W* buf) {
+    constexpr int S = (N + 63) / 64;
+    constexpr int RW = jump_row_words<N, true>();
+    constexpr int SET = RW + jump_pad_words<N>();  // words of one row set
+    constexpr int PARTS = 15;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    state = uniform(state);
+    poly = uniform(poly);
+    k = (int)uniform((uint32_t)k);
+    max_deg = (int)uniform((uint32_t)max_deg);
+    M = uniform(M);
+    W* gwin = reinterpret_cast<W*>(state + kHeaderBytes);
+    uint64_t* spoly = reinterpret_cast<uint64_t*>(buf + 2 * SET);
+    W* cur = buf;
+    W* nxt = buf + SET;
+    for (int j = tid; j < N; j += nthr) cur[j] = gwin[(size_t)j * M + lane0];
+    for (int i = tid; i <= (max_deg >> 6); i += nthr) spoly[i] = poly[i];
+    __syncthreads();
+    twist_rows<W, N>(cur, cur + N, 1, RW, tid, nthr);
+    __syncthreads();
+    derive_rows<W, N>(cur, 1, 2 * N, RW, tid, nthr);
+    __syncthreads();
+
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    const int last_b = (k + max_deg) / N;
+    for (int b = 0; b <= last_b; ++b) {
+        if (wave > 0) {
+            accumulate_block4<W, N, true>(acc, cur, 2 * N, spoly, k, b, max_deg, lane, wave - 1, PARTS);
+        } else if (b < last_b) {
+            for (int j = lane; j < N; j += 64) nxt[j] = cur[N + j];  // lower half: the current upper block
+            twist_rows<W, N>(cur + N, nxt + N, 1, RW, lane, 64);     // upper half: the next block
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wavefront's window writes are done
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            derive_rows<W, N>(nxt, 1, 2 * N, RW, lane, 64);
+        }
+        __syncthreads();
+        W* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    // XOR the slices' sums (wavefronts 1 .. 15) and store the lane's window
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = lane + 64 * s;
+        if (wave > 0 && j < N) buf[(wave - 1) * N + j] = acc[s];
+    }
+    __syncthreads();
+    for (int j = tid; j < N; j += nthr) {
+        W v = buf[j];
+#pragma unroll
+        for (int q = 1; q < PARTS; ++q) v = xorw(v, buf[q * N + j]);
+        gwin[(size_t)j * M + lane0] = v;
+    }
+}
+
 template <class W, int N, int G, bool GROUPED, int WPL = 1>
 __global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* tasks, JumpTask one, uint32_t M) {
-    constexpr int EXTRA = (WPL > 1 ? jump_pad_words<N>() : 0) + (WPL >= 8 ? jump_poly_stage_words<W>() : 0);
+    // SFMT: two row sets (jump_pipelined), the serial chain of the next block
+    // overlapping the sums of this one. MT regenerates its rows in parallel:
+    // one wavefront building them alone is slower than all of them in turn.
+    constexpr bool PIPE = GROUPED && G == 1 && WPL == 16 && sizeof(W) == 16;
+    constexpr int EXTRA = (WPL > 1 ? jump_pad_words<N>() : 0) + (WPL >= 8 ? jump_poly_stage_words<W>() : 0) +
+                          (PIPE ? jump_row_words<N, true>() + jump_pad_words<N>() : 0);
     __shared__ __attribute__((aligned(16))) W buf[jump_row_words<N, GROUPED>() * G + EXTRA];
     const uint32_t groups = M / G;
     const uint32_t ti = blockIdx.x / groups, g = blockIdx.x - ti * groups;
@@ -1189,8 +1263,12 @@ __global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* task
     const StateHeader* h = reinterpret_cast<const StateHeader*>(task.state);
     const uint32_t per = sizeof(W) == 16 ? 4u : 1u;
     const int k = (int)(h->pos / (per * M));  // words of every lane already consumed
-    dephase<W, N, G, false, GROUPED, WPL>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k,
-                                          nullptr, buf);
+    if constexpr (PIPE) {
+        jump_pipelined<W, N>(task.state, M, g, task.poly + (size_t)task.lane_stride * g, (int)task.max_deg, k, buf);
+    } else {
+        dephase<W, N, G, false, GROUPED, WPL>(task.state, M, g, task.poly, task.lane_stride, (int)task.max_deg, k,
+                                              nullptr, buf);
+    }
 }
 
 // Jumps of one state's copies by different distances (the chunks of a split
