@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "aa7fd6d81b5773298c74a82fd4d973c6fa88cba5b7c75266c6a1296d81e1ea66",
+    "kernel_fingerprint": "5a70c1e2a717e4f9e7247ab91b8a635657be1c592f85c1f1adc3a78c89932e71",
     "shapes": {
-        (512, 16, 2): (877941333, 96283547893),
-        (512, 8, 2): (878038699, 96283547797),
-        (256, 16, 2): (878112981, 96283547797),
-        (256, 8, 3): (878321408, 96283564288),
-        (960, 16, 2): (878084992, 96283549440),
+        (512, 16, 2): (878044331, 96283548107),
+        (512, 8, 2): (878088448, 96283547851),
+        (256, 16, 2): (878164693, 96283547797),
+        (256, 8, 3): (878276779, 96283564341),
+        (960, 16, 2): (878073088, 96283549333),
     },
 }
 
