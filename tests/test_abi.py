@@ -90,3 +90,20 @@ def test_library_jump_poly_small_distances_match_oracle():
                 assert vmt.vmt_jump_poly(ctx, variant, d) == O.poly_powmod_t(d, mu), (variant, d)
     finally:
         vmt.vmt_ctx_destroy(ctx)
+
+
+def test_library_jump_poly_lane_distances_match_oracle_fixtures():
+    # the general distance path at the sizes of real jumps: J + d for the lane distance J = 2^(MEXP - 4) of M = 16
+    # (square-and-multiply over ~20k bits in the library) against the oracle's stored t^J times t^d
+    from oracle import pyoracle as O
+    from paper_2309_16682_amd import vmt
+
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        for variant, d in ((0, 12345), (1, 7), (2, 99999), (7, 3)):
+            mu = golden_io.minpoly(variant)
+            J = 1 << (golden_io.MEXP[variant] - 4)
+            ref = O.poly_mulmod(golden_io.lane_poly(variant, 16), O.poly_powmod_t(d, mu), mu)
+            assert vmt.vmt_jump_poly(ctx, variant, J + d) == ref, variant
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
