@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--only-single", type=str, default=None,
                     help="run these single-stream configurations only (comma-separated names, e.g. sfmt_M4_2^28_u32)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--single-shape", type=str, default=None,
+                    help="with --only-single: LANES_PER_WG,SPLIT_LOG2 instead of autotuning the generate family")
     ap.add_argument("--no-graph", action="store_true", help="launch the rounds eagerly instead of replaying a graph")
     ap.add_argument("--tune-sample", type=int, default=8192)
     ap.add_argument("--shape", type=str, default=None,
@@ -250,7 +252,10 @@ def single_streams(ctx, torch, args, only=None) -> dict:
             continue
         okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
         lpw = split = None
-        if not args.no_autotune:
+        if args.single_shape:  # a fixed shape (profiling one configuration): lanes per workgroup, log2 chunk
+            lpw, split = (int(x) for x in args.single_shape.split(","))
+            vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, lanes_per_wg=lpw, split_log2=split)
+        elif not args.no_autotune:
             b, tried = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [n], reps=2)
             lpw = b.lanes_per_wg
             split = b.split_log2
