@@ -15,9 +15,15 @@
  *     map must carry an irreducible factor of degree 19937); value-level
  *     output for a given seed: parity unpinned (no published check output is
  *     available here).
- *   SFMT19937 seeding / period certification constants: pinned algebraically
- *     (the parity vector must annihilate the complement of the degree-19937
- *     component); the bit-exact seeded state itself: parity unpinned.
+ *   SFMT seeding (every parameter set): the init_genrand loop over the 4N
+ *     sub-words is pinned by numpy RandomState(seed), whose 624 words it must
+ *     reproduce up to the certification flip; the certification constants
+ *     are pinned algebraically (the parity vector must annihilate the
+ *     complement of the degree-MEXP component). Which bit the certification
+ *     flips (the lowest set bit of the parity vector) and the order in which
+ *     the sub-words of a 128-bit word are emitted: parity unpinned (fixed by
+ *     the generator's authors, not by the paper, and no published check
+ *     output is available here).
  *   Minimal polynomial, powers of t, jump: pinned by brute-force stepping,
  *     composition, the period identity and the Frobenius identity.
  */

@@ -160,8 +160,33 @@ def test_sfmt_certified_state_has_odd_parity(seed):
     assert _parity(x, (1, 0, 0, 0x13C9E684)) == 1
 
 
+@pytest.mark.parametrize("variant", O.SFMT_FAMILY)
+@pytest.mark.parametrize("seed", [0, 1, 1234, 4321, 5489, 2**32 - 1])
+def test_sfmt_seeding_is_init_genrand_over_the_sub_words(variant, seed):
+    # Pin of the seeding loop (reading C6) outside the oracle: SFMT seeds its 4N
+    # 32-bit sub-words with MT19937's init_genrand, which numpy's
+    # RandomState(seed) runs over 624 words, and 4N <= 624 for every set. The
+    # only allowed difference is the period certification: word 0 with the
+    # lowest set bit of the set's parity vector flipped, exactly when the
+    # parity of <PARITY, w_0> of numpy's words is even.
+    n4 = O.STATE_LEN[variant]
+    ref = np.random.RandomState(seed).get_state()[1][:n4].astype(np.uint32)
+    got = O.seed_state(variant, seed)
+    parity = [int(v) for v in O.sfmt_parity(variant)]
+    diff = np.nonzero(got != ref)[0]
+    even = _parity(ref[:4], parity) == 0
+    if even:
+        j = next(j for j in range(4) if parity[j])
+        low = parity[j] & -parity[j]
+        assert list(diff) == [j] and int(got[j]) ^ int(ref[j]) == low
+    else:
+        assert len(diff) == 0
+    assert O.sfmt_certification_flipped(seed, variant) == even
+
+
 def test_sfmt_seed_1234_certification_flips():
-    # recorded reading: for seed 1234 the certification fires (bit 0 of w_0)
+    # a recorded reading, not a pin: for SFMT19937 and seed 1234 the
+    # certification fires (bit 0 of w_0); the numpy test above fixes when
     assert O.sfmt_certification_flipped(1234)
 
 
