@@ -104,6 +104,7 @@ def parse():
     ap.add_argument("--single-shape", type=str, default=None,
                     help="with --only-single: LANES_PER_WG,SPLIT_LOG2 instead of autotuning the generate family")
     ap.add_argument("--no-graph", action="store_true", help="launch the rounds eagerly instead of replaying a graph")
+    ap.add_argument("--no-pattern", action="store_true", help="skip timing the output pattern without the twist")
     ap.add_argument("--tune-sample", type=int, default=8192)
     ap.add_argument("--shape", type=str, default=None,
                     help="fix the batch shape as threads_variant,store_bytes,wg_per_cu (no autotuning)")
@@ -185,11 +186,12 @@ def cpu_baseline(seconds: float, threads: int) -> dict:
     }
 
 
-def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
+def calibrate(torch, ctx=None, gib: int = 4, reps: int = 3) -> dict:
     """A plain device copy (read n + write n bytes), fill (torch's 16-byte
-    vector stores) and hipMemsetAsync (write n bytes) of `gib` GiB: the copy's
-    FETCH_SIZE / WRITE_SIZE readings give the counters' scale, the fill and
-    memset rates the write ceiling measured on this device."""
+    vector stores), hipMemsetAsync and the library's own 16-byte fill, plain
+    and nontemporal (write n bytes) of `gib` GiB: the copy's FETCH_SIZE /
+    WRITE_SIZE readings give the counters' scale, the fill and memset rates
+    the write ceiling measured on this device."""
     n = gib << 30
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -204,8 +206,13 @@ def calibrate(torch, gib: int = 4, reps: int = 3) -> dict:
     def memset():
         assert hip.hipMemsetAsync(ctypes.c_void_p(dst.data_ptr()), 7, n, stream) == 0
 
-    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * n), ("fill", lambda: dst.fill_(7), n),
-                            ("memset", memset, n)):
+    legs = [("copy", lambda: dst.copy_(src), 2 * n), ("fill", lambda: dst.fill_(7), n), ("memset", memset, n)]
+    if ctx is not None:
+        from paper_2309_16682_amd import vmt
+
+        legs += [("fill_lib", lambda: vmt.vmt_calib_fill(ctx, dst), n),
+                 ("fill_lib_nt", lambda: vmt.vmt_calib_fill(ctx, dst, nontemporal=True), n)]
+    for name, fn, moved in legs:
         fn()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -446,7 +453,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate:
-        print(json.dumps(calibrate(torch)), flush=True)
+        ctx = vmt.vmt_ctx_create(0)
+        print(json.dumps(calibrate(torch, ctx)), flush=True)
+        vmt.vmt_ctx_destroy(ctx)
         return
     if args.only_single:
         ctx = vmt.vmt_ctx_create(0)
@@ -468,7 +477,7 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = vmt.vmt_ctx_create(0)
 
-    ceiling = calibrate(torch)  # measured write ceiling on this device, before the big allocations
+    ceiling = calibrate(torch, ctx)  # measured write ceiling on this device, before the big allocations
     torch.cuda.empty_cache()
     log(f"device copy/fill: {ceiling}")
 
@@ -575,6 +584,25 @@ def main():
     value = step_out_bytes / (ms_per_step * 1e-3) / 1e9
     log(f"batched: {ms_per_step:.2f} ms/step, {value:.1f} GB/s output; kernel avg {launch_ms_mean:.3f} ms/launch")
 
+    # the ceiling of this output pattern: the same plans and launch shape with the twist left out
+    # (vmt_batch_plan_write_pattern: same queue, stores and state traffic; states unchanged)
+    pattern_ms = None
+    if not args.no_pattern:
+        with torch.cuda.stream(run_stream):
+            for p in plans:
+                vmt.vmt_batch_plan_write_pattern(p, run_stream)
+        torch.cuda.synchronize()
+        pa, pb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        preps = 2
+        pa.record(run_stream)
+        for _ in range(preps):
+            for p in plans:
+                vmt.vmt_batch_plan_write_pattern(p, run_stream)
+        pb.record(run_stream)
+        torch.cuda.synchronize()
+        pattern_ms = pa.elapsed_time(pb) / (preps * len(plans))
+        log(f"write pattern without the twist: {pattern_ms:.3f} ms/launch")
+
     result = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -614,6 +642,10 @@ def main():
             "measured_fill_GBps": ceiling["fill_GBps"],
             "measured_memset_GBps": ceiling["memset_GBps"],
             "frac_of_measured_fill": round(achieved / ceiling["fill_GBps"], 4),
+            "measured_fill_lib_GBps": ceiling.get("fill_lib_GBps"),
+            "measured_fill_lib_nt_GBps": ceiling.get("fill_lib_nt_GBps"),
+            "pattern_ceiling_GBps": round(np.mean(round_alg_bytes) / (pattern_ms * 1e-3) / 1e9, 1) if pattern_ms else None,
+            "frac_of_pattern_ceiling": round(launch_ms_mean and pattern_ms / launch_ms_mean, 4) if pattern_ms else None,
             "alg_bytes_per_launch": int(np.mean(round_alg_bytes)),
         },
         "init": {"generators": G, "device_ms": round(init_ms, 2), "lane_jumps": G * (M_LANES - 1),

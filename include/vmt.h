@@ -80,25 +80,38 @@ extern "C" {
 
 typedef struct vmt_ctx vmt_ctx;
 
-/* Thread-local text of the last error on this thread ("" if none). */
+/* Thread-local text of the last error on this thread ("" if none).
+ * Cite: paper silent; error reporting of this C ABI.
+ */
 const char* vmt_last_error(void);
 
-/* Library version string. */
+/* Library version string.
+ * Cite: paper silent; library identification.
+ */
 const char* vmt_version(void);
 
 /* Create a context on HIP device `device`. On failure returns NULL and, if
  * status is not NULL, stores the error code there. The context computes the
  * minimal polynomials of the three base generators and the lane polynomials
- * it needs lazily, on the host, and keeps them for its lifetime. */
+ * it needs lazily, on the host, and keeps them for its lifetime.
+ * Cite: paper silent on contexts; it holds the minimal polynomials of Sec. 3.1 (jump polynomial t^d
+ * mod mu) and the lane polynomials t^(tJ) of eq. (jumpahead). No cache directory: the host
+ * polynomials of a context take about 0.03 s.
+ */
 vmt_ctx* vmt_ctx_create(int device, int* status);
 
-/* Destroy a context: frees its device tables. Waits for the device. */
+/* Destroy a context: frees its device tables. Waits for the device.
+ * Cite: paper silent; releases what vmt_ctx_create built.
+ */
 int vmt_ctx_destroy(vmt_ctx* ctx);
 
 /* Bytes of device memory a state of `variant` with M lanes occupies: a
  * 256-byte header plus the lane-interleaved window, n words x M lanes
  * (word k of lane t at index k*M + t). M must be a power of two in [1, 64].
- * Returns 0 for an invalid variant or M. */
+ * Returns 0 for an invalid variant or M.
+ * Cite: Sec. 3, eq. (msmt19937) (the interleaved state of M instances) with the n words per
+ * instance of Sec. 2.2-2.4 and the circular buffer of Sec. 2.5, eq. (staterec).
+ */
 size_t vmt_state_bytes(int variant, uint32_t M);
 
 /* Initialise a V-state (Sec. 3, Sec. 3.1). The base state X_0 comes from
@@ -107,19 +120,27 @@ size_t vmt_state_bytes(int variant, uint32_t M);
  * seed, SFMT then applies its period certification. Lane t becomes X_0
  * advanced by t*J steps, J = 2^(19937 - log2 M). The first element of the
  * stream is the base generator's first output. d_state must hold
- * vmt_state_bytes(variant, M) bytes of device memory, 256-byte aligned. */
+ * vmt_state_bytes(variant, M) bytes of device memory, 256-byte aligned.
+ * Cite: Sec. 3 eq. (subseq) and Sec. 3.1 eq. (jumpahead) (lane t = X_0 advanced t J steps, J from
+ * Table jvalues); seeding itself: paper silent, the generators' published init_genrand.
+ */
 int vmt_init_genrand(vmt_ctx* ctx, int variant, uint64_t seed, uint32_t M, void* d_state,
                      hipStream_t stream);
 
 /* As vmt_init_genrand, with X_0 from init_by_array(key[0..key_len-1]) of the
  * MT19937 release (host array). MT19937-32 only (VMT_EVARIANT otherwise);
- * 1 <= key_len <= 4096. */
+ * 1 <= key_len <= 4096.
+ * Cite: as vmt_init_genrand; the key expansion is paper silent (MT19937's published init_by_array).
+ */
 int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key_len, uint32_t M,
                       void* d_state, hipStream_t stream);
 
 /* Batched vmt_init_by_array: count states, state i keyed by
  * keys[i*key_len .. i*key_len + key_len - 1] (host array), all MT19937-32
- * with M lanes; d_states is a host array of count device pointers. */
+ * with M lanes; d_states is a host array of count device pointers, each
+ * state at most once (VMT_EINVAL otherwise).
+ * Cite: as vmt_init_by_array; batching many generators: paper silent.
+ */
 int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, size_t count,
                             uint32_t M, void* const* d_states, hipStream_t stream);
 
@@ -127,15 +148,24 @@ int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, 
  * skips d*M elements (4*d*M uint32 for SFMT19937). d is the little-endian
  * multiword integer dist_le[0..dist_words-1] (host array; dist_words <= 320).
  * The jump polynomial t^d mod (minimal polynomial) is computed on the host
- * and cached per distance; the state is updated on the device. */
+ * and cached per distance; the state is updated on the device.
+ * Cite: Sec. 3.1, eq. (jumpahead) and the polynomial jump the paper cites as the alternative to eq.
+ * (transmat); on a V-state: every lane advances d steps (eq. (subseq)), so eq. (combseq)'s stream
+ * skips d M elements.
+ */
 int vmt_jump(vmt_ctx* ctx, void* d_state, const uint64_t* dist_le, size_t dist_words,
              hipStream_t stream);
 
-/* vmt_jump with d = 2^k, k <= 65536. */
+/* vmt_jump with d = 2^k, k <= 65536.
+ * Cite: as vmt_jump.
+ */
 int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream);
 
 /* Batched jump by 2^k: count states (host array of device pointers), state i
- * jumped by 2^ks[i]; all states must share variant and M. */
+ * jumped by 2^ks[i]; all states must share variant and M, each state at most
+ * once (VMT_EINVAL otherwise).
+ * Cite: as vmt_jump; batching: paper silent.
+ */
 int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count,
                         hipStream_t stream);
 
@@ -143,14 +173,20 @@ int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks,
  * generate_u32: MT19937-32 and SFMT19937. generate_u64: MT19937-64. n may be
  * 0. A long call may run split over many workgroups (see "Splitting" below):
  * the outputs are the same; the state afterwards is the same point of the
- * stream, possibly on a shifted block grid (as after any jump). */
+ * stream, possibly on a shifted block grid (as after any jump).
+ * Cite: Sec. 2.1 eq. (formula) (a generator yields w-bit words), Sec. 3 eq. (combseq) (the round
+ * robin of the M instances), the bulk (vectorial) query mode of Sec. 4.3.
+ */
 int vmt_generate_u32(vmt_ctx* ctx, void* d_state, size_t n, uint32_t* d_out, hipStream_t stream);
 int vmt_generate_u64(vmt_ctx* ctx, void* d_state, size_t n, uint64_t* d_out, hipStream_t stream);
 
 /* Uniform floats in [0, 1) by fixed exact maps of the stream elements, one
  * element per output: f32 = (u32 >> 8) * 2^-24 for MT19937-32 and SFMT19937,
  * (u64 >> 40) * 2^-24 for MT19937-64; f64 = (u64 >> 11) * 2^-53 for
- * MT19937-64 (VMT_EVARIANT for the 32-bit generators). */
+ * MT19937-64 (VMT_EVARIANT for the 32-bit generators).
+ * Cite: paper silent (it generates integers only); the maps are the fixed exact integer-to-float
+ * conversions of the workloads measured here, applied to the eq. (combseq) stream.
+ */
 int vmt_uniform_f32(vmt_ctx* ctx, void* d_state, size_t n, float* d_out, hipStream_t stream);
 int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStream_t stream);
 
@@ -159,23 +195,48 @@ int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStr
  * states must share variant and M. MT19937-32/-64 (M <= 16): one persistent
  * kernel processes the states longest first from a device work queue.
  * SFMT19937: one workgroup per state and group of up to 16 lanes. Each state
- * must appear at most once per call. */
+ * must appear at most once per call.
+ * Cite: paper silent (the paper runs one generator at a time); each state is the V-generator of
+ * Sec. 3, eq. (combseq).
+ */
 int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
                        size_t count, int out_kind, hipStream_t stream);
 
 /* Plan form of vmt_batch_generate for repeated replay: uploads the task list
  * once and returns a handle whose launch reuses it (the same states, lengths
  * and outputs each time; states advance on every launch). The launch can be
- * captured into a HIP graph by the caller. */
+ * captured into a HIP graph by the caller.
+ * Cite: as vmt_batch_generate.
+ */
 typedef struct vmt_batch_plan vmt_batch_plan;
 vmt_batch_plan* vmt_batch_plan_create(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens,
                                       void* const* d_outs, size_t count, int out_kind, int* status);
 int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream);
 int vmt_batch_plan_destroy(vmt_batch_plan* plan);
 
+/* Measurement only (paper silent; the write ceiling the generation rate is
+ * compared with). vmt_batch_plan_write_pattern enqueues the plan's batch
+ * kernel with the twist left out: the same task queue, launch shape, window
+ * reads and writes and output stores of the same lengths to the same
+ * addresses, so its rate is what the plan's output pattern allows. The
+ * outputs receive tempered words of the unchanged windows (not stream
+ * values) and the states are left as they were. V-MT19937-32 M=16 uint32 and
+ * V-MT19937-64 M=8 uint64 plans (VMT_EVARIANT otherwise). Must not overlap a
+ * launch of the same plan (they share its queue counter).
+ * vmt_calib_fill writes `bytes` (a multiple of 16, 16-byte aligned buffer)
+ * with 16-byte stores, 4 KiB per workgroup and step, nontemporal if
+ * `nontemporal` is nonzero: the plain write ceiling.
+ * Cite: paper silent; a measurement aid.
+ */
+int vmt_batch_plan_write_pattern(vmt_batch_plan* plan, hipStream_t stream);
+int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int nontemporal, hipStream_t stream);
+
 /* Copy a state to or from host memory (bytes = vmt_state_bytes). Import
  * validates the header and registers the state with the context. Both
- * synchronise `stream`. */
+ * synchronise `stream`.
+ * Cite: Sec. 3, eq. (msmt19937): the state is the interleaved window of the M instances; the copy
+ * format itself: paper silent.
+ */
 int vmt_state_export(vmt_ctx* ctx, const void* d_state, void* h_buf, size_t bytes, hipStream_t stream);
 int vmt_state_import(vmt_ctx* ctx, void* d_state, const void* h_buf, size_t bytes, hipStream_t stream);
 
@@ -212,7 +273,8 @@ typedef struct {
 
 typedef struct vmt_server vmt_server;
 
-/* d_states: host array of n_states registered device states; d_arena:
+/* d_states: host array of n_states registered device states (each at most
+ * once, VMT_EINVAL otherwise); d_arena:
  * 256-byte aligned device memory; out_kind: VMT_OUT_* of the generated
  * elements; 1 <= n_streams <= 16 generation streams (mode 0 adds two jump
  * streams); mode: bit 0 plain launches, bit 1 retain, bit 2 split.
@@ -225,14 +287,19 @@ typedef struct vmt_server vmt_server;
  * run side by side: chunk c from the state jumped by c * 2^v steps (Sec. 3.1;
  * a jump of d steps skips d * M stream words), chunks 0 .. C-2 on copies in
  * scratch states of the server (2048 of them; a request waits for enough
- * free ones), the last on the state itself. 0 = one task per request. */
+ * free ones), the last on the state itself. 0 = one task per request.
+ * Cite: paper silent (no serving in the paper); requests are generation (Sec. 3, eq. (combseq)) and
+ * jumps by 2^k (Sec. 3.1).
+ */
 vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_states, void* d_arena,
                               size_t arena_bytes, uint64_t budget_bytes, int out_kind, uint32_t n_streams,
                               int mode, uint64_t chunk_elems, int* status);
 /* Serve n requests. realtime = 1: request i becomes visible at its
  * t_arrival (host clock from the start of the call); 0: all at once.
  * results (host array of n) receives the timeline of each request; *wall_s
- * the duration of the run. Blocks until every request has completed. */
+ * the duration of the run. Blocks until every request has completed.
+ * Cite: as vmt_server_create.
+ */
 int vmt_server_run(vmt_server* server, const vmt_request* reqs, size_t n, vmt_result* results, int realtime,
                    double* wall_s);
 /* Bound on how long a run may go with work in flight and no request
@@ -245,18 +312,25 @@ int vmt_server_run(vmt_server* server, const vmt_request* reqs, size_t n, vmt_re
  * splitting) with launch >= 0 has therefore written its whole output and
  * advanced its state past it; a chunked or split one may stop part-way.
  * seconds = 0 gives up at the first check with anything in flight, which
- * forces this path from the host. The server stays usable. */
+ * forces this path from the host. The server stays usable.
+ * Cite: paper silent; failure handling of the serving loop.
+ */
 int vmt_server_set_watchdog(vmt_server* server, double seconds);
 int vmt_server_destroy(vmt_server* server);
 
 /* Forget a state: the context's registry is keyed by device address, so a
  * caller that frees a state's memory should release it first (a later
- * allocation at the same address must be initialised or imported again). */
+ * allocation at the same address must be initialised or imported again).
+ * Cite: paper silent; registry bookkeeping.
+ */
 int vmt_state_release(vmt_ctx* ctx, const void* d_state);
 
 /* Host helpers (no device work). Minimal polynomial of the one-step map of a
  * base generator and t^d mod it, as little-endian bit arrays (bit i of the
- * uint64 array = coefficient of t^i); cap = words available in out. */
+ * uint64 array = coefficient of t^i); cap = words available in out.
+ * Cite: Sec. 3.1 (the jump polynomial is t^d modulo the minimal polynomial of the one-step map, eq.
+ * (matmult)); computing mu by Berlekamp-Massey: paper silent.
+ */
 int vmt_minpoly(vmt_ctx* ctx, int variant, uint64_t* out, size_t cap, int* degree);
 int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dist_words, uint64_t* out,
                   size_t cap, int* degree);
@@ -282,7 +356,10 @@ int vmt_jump_poly(vmt_ctx* ctx, int variant, const uint64_t* dist_le, size_t dis
  *     (degree 19937 + 31 M).
  *
  * vmt_check_poly writes A (bit i of out = coefficient of t^i; cap words
- * available) and its degree; host only. */
+ * available) and its degree; host only.
+ * Cite: Sec. 4.1 (LinearComp, the test every MT-based generator fails) and eq. (combseq) with J
+ * from Table jvalues.
+ */
 int vmt_check_poly(vmt_ctx* ctx, int variant, uint32_t M, uint64_t* out, size_t cap, int* degree);
 
 /* Count the offsets at which a generated stream breaks its recurrence. The
@@ -301,7 +378,9 @@ int vmt_check_poly(vmt_ctx* ctx, int variant, uint32_t M, uint64_t* out, size_t 
  * VMT_EINVAL if n_words <= deg(A) S (nothing to check), VMT_EVARIANT for an
  * out kind the variant does not produce (u64 or f64 of the 32-bit
  * generators). Allocates nothing after the first call for a (variant, M):
- * the device copy of A stays with the context. */
+ * the device copy of A stays with the context.
+ * Cite: as vmt_check_poly.
+ */
 int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const void* d_out, uint64_t n,
                      uint64_t* d_count, hipStream_t stream);
 
@@ -346,7 +425,10 @@ typedef struct {
 } vmt_shape;
 
 /* Shape in force; set stores one (NULL: back to the default). VMT_EINVAL for
- * a shape that is not compiled in. */
+ * a shape that is not compiled in.
+ * Cite: paper silent; launch shapes of this GPU implementation (the paper's analogue is the SIMD
+ * width L of Table jvalues).
+ */
 int vmt_shape_get(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, vmt_shape* shape);
 int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const vmt_shape* shape);
 
@@ -358,7 +440,9 @@ int vmt_shape_set(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kin
  * untimed and `reps` times timed with HIP events on `stream`; the fastest
  * repetition counts. tried (optional, tried_cap entries) receives every shape
  * timed, *n_tried their number. Synchronises `stream`; VMT_ENOMEM if the
- * scratch outputs do not fit. */
+ * scratch outputs do not fit.
+ * Cite: paper silent; chooses among launch shapes that all give the same bits.
+ */
 int vmt_autotune(vmt_ctx* ctx, int family, int variant, uint32_t M, int out_kind, const uint64_t* lens,
                  size_t count, int reps, vmt_shape* best, vmt_shape* tried, size_t tried_cap, size_t* n_tried,
                  hipStream_t stream);

@@ -563,12 +563,8 @@ int validate_batch_args(vmt_ctx* ctx, void* const* d_states, const uint64_t* len
     if (!ok)
         return fail(VMT_EVARIANT, "batched output kind %d not available for variant %d with M=%u", out_kind,
                     info->variant, info->M);
-    {
-        std::vector<const void*> seen(d_states, d_states + count);
-        std::sort(seen.begin(), seen.end());
-        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
-            return fail(VMT_EINVAL, "a state appears twice in one batch");
-    }
+    st = vmt::reject_duplicate_states(d_states, count);
+    if (st) return st;
     for (size_t i = 0; i < count; i++) {
         if (lens[i] && !d_outs[i]) return fail(VMT_EINVAL, "null output for task %zu", i);
         if ((uintptr_t)d_outs[i] % out_elem_bytes(out_kind))
@@ -626,6 +622,15 @@ int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly
 }
 
 int ctx_device(vmt_ctx* ctx) { return ctx->device; }
+
+int reject_duplicate_states(void* const* d_states, size_t count) {
+    if (count < 2) return VMT_OK;
+    std::vector<const void*> seen(d_states, d_states + count);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return set_error(VMT_EINVAL, "a state appears twice in one call");
+    return VMT_OK;
+}
 
 int ctx_split_polys(vmt_ctx* ctx, int variant, int v, size_t need, const uint64_t** d_table,
                     std::vector<uint32_t>* degrees) {
@@ -741,14 +746,16 @@ int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key
 
 int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, size_t count, uint32_t M,
                             void* const* d_states, hipStream_t stream) {
-    int st = set_device(ctx);
-    if (st) return st;
     if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
-    if (count == 0) return VMT_OK;
+    if (count == 0) return set_device(ctx);
     if (!keys || !d_states || key_len == 0 || key_len > 4096) return fail(VMT_EINVAL, "bad keys");
     if (count > (1u << 24)) return fail(VMT_EINVAL, "too many states");
     for (size_t i = 0; i < count; i++)
         if (!d_states[i] || (uintptr_t)d_states[i] % 256) return fail(VMT_EINVAL, "state %zu null or misaligned", i);
+    int st = vmt::reject_duplicate_states(d_states, count);  // two seedings of one window would race
+    if (st) return st;
+    st = set_device(ctx);
+    if (st) return st;
     LaneTable* lt = nullptr;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -810,10 +817,12 @@ int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream) {
 }
 
 int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks, size_t count, hipStream_t stream) {
-    int st = set_device(ctx);
+    if (count == 0) return set_device(ctx);
+    if (!ks || !d_states) return fail(VMT_EINVAL, "null ks or states");
+    int st = vmt::reject_duplicate_states(d_states, count);  // two jumps of one window in place would race
     if (st) return st;
-    if (count == 0) return VMT_OK;
-    if (!ks) return fail(VMT_EINVAL, "null ks");
+    st = set_device(ctx);
+    if (st) return st;
     StateInfo info;
     st = check_batch(ctx, d_states, count, &info);
     if (st) return st;
@@ -923,6 +932,27 @@ int vmt_batch_plan_launch(vmt_batch_plan* plan, hipStream_t stream) {
     hipError_t e = launch_tasks(plan->variant, plan->M, plan->out_kind, plan->shape, plan->d_tasks, plan->count,
                                 plan->d_counter, stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return VMT_OK;
+}
+
+int vmt_batch_plan_write_pattern(vmt_batch_plan* plan, hipStream_t stream) {
+    if (!plan) return fail(VMT_EINVAL, "null plan");
+    int st = set_device(plan->ctx);
+    if (st) return st;
+    if (!vmt::pattern_supported(plan->variant, plan->M, plan->out_kind))
+        return fail(VMT_EVARIANT, "write pattern: only V-MT19937-32 M=16 uint32 and V-MT19937-64 M=8 uint64 plans");
+    hipError_t e = vmt::launch_write_pattern(plan->variant, plan->M, plan->out_kind, plan->shape, plan->d_tasks,
+                                             plan->count, plan->d_counter, stream);
+    if (e != hipSuccess) return hip_fail(e, "write pattern launch");
+    return VMT_OK;
+}
+
+int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int nontemporal, hipStream_t stream) {
+    int st = set_device(ctx);
+    if (st) return st;
+    if (!d_buf || bytes % 16 || (uintptr_t)d_buf % 16) return fail(VMT_EINVAL, "fill: buffer and size must be 16-byte aligned");
+    hipError_t e = vmt::launch_fill(d_buf, bytes, nontemporal != 0, vmt::device_cus(ctx->device), stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
     return VMT_OK;
 }
 

@@ -18,6 +18,9 @@ int ctx_state_info(vmt_ctx* ctx, const void* d_state, int* variant, uint32_t* M)
 // Device copy of t^(2^k) mod mu for `variant` (cached by the context) and its degree.
 int ctx_pow2_poly(vmt_ctx* ctx, int variant, uint32_t k, const uint64_t** d_poly, uint32_t* degree);
 
+// VMT_EINVAL (with the message set) if a state pointer occurs twice in the list.
+int reject_duplicate_states(void* const* d_states, size_t count);
+
 // Device the context runs on (-1 for a host-only context).
 int ctx_device(vmt_ctx* ctx);
 

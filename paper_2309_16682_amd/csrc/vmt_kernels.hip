@@ -560,6 +560,47 @@ struct MtGen {
         if (write_pos && uniform((uint32_t)tid >> 6) == 0)  // wave 0, same value from every lane
             gstore(&hdr->pos, nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head));
     }
+
+    // Measurement only: run()'s memory traffic with the twist left out. The
+    // window is read, every block of the request is stored from the unchanged
+    // window through the same store path (the twist's two barriers kept), and
+    // the window is written back unchanged; the position is not advanced, so
+    // the state is left as it was.
+    static __device__ __forceinline__ void run_pattern(uint8_t* state, OutT* out, uint64_t len, W* win) {
+        state = uniform(state);
+        out = uniform(out);
+        len = uniform(len);
+        StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
+        const uint32_t M = uniform(gload(&hdr->M));
+        const uint32_t pos = uniform(gload(&hdr->pos));
+        W* gwin = reinterpret_cast<W*>(state + kHeaderBytes);
+        const uint32_t B = (uint32_t)N * M;
+        if (len == 0) return;
+        const int tid = threadIdx.x;
+        const uint64_t head = len < (uint64_t)(B - pos) ? len : (uint64_t)(B - pos);
+        const uint64_t rest = len - head;
+        const uint64_t nblocks = (rest + B - 1) / B;
+        for (int i = tid; i < N * QPR; i += THREADS) {
+            const int k = i / QPR, q = i - (i / QPR) * QPR;
+            st(win, k, q * V, gload(reinterpret_cast<const VW*>(gwin + (size_t)k * M + q * V)));
+        }
+        __syncthreads();
+        if (head) store(win, out, pos, pos + (uint32_t)head, 0, M, 0, tid);
+        for (uint64_t b = 0; b < nblocks; ++b) {
+            const uint64_t o0 = head + b * B;
+            __syncthreads();
+            __syncthreads();
+            const uint32_t n = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
+            store(win, out, 0, n, o0, M, 0, tid);
+        }
+        if (nblocks) {
+            __syncthreads();
+            for (int i = tid; i < N * QPR; i += THREADS) {
+                const int k = i / QPR, q = i - (i / QPR) * QPR;
+                gstore(reinterpret_cast<VW*>(gwin + (size_t)k * M + q * V), ld(win, k, q * V));
+            }
+        }
+    }
 };
 
 template <class P, int LPW, int OUT>
@@ -615,6 +656,50 @@ __global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) vo
             counter[0] = 0;
             counter[1] = 0;
         }
+    }
+}
+
+// Measurement only: the output pattern of batch_mt_kernel (same queue, same
+// launch shape, same stores of the same lengths to the same places) without
+// the twist, i.e. the write rate that pattern allows. States are unchanged.
+template <class P, int LANES, int TV, int SW>
+__global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) void write_pattern_kernel(
+    const BatchTask* tasks, uint32_t count, uint32_t* counter) {
+    using G = MtGen<P, LANES, mt_threads<P, LANES, TV>(), 0, SW>;
+    __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LANES];
+    __shared__ uint32_t s_task;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    for (;;) {
+        if (wave == 0) {
+            const uint32_t mine = atomicAdd(counter, lane == 0 ? 1u : 0u);
+            s_task = uniform(mine);
+        }
+        __syncthreads();
+        const uint32_t t = uniform(s_task);
+        __syncthreads();
+        if (t >= count) break;
+        const BatchTask task = tasks[t];
+        G::run_pattern(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, win);
+    }
+    if (wave == 0) {
+        const uint32_t done = uniform(atomicAdd(counter + 1, lane == 0 ? 1u : 0u));
+        if (done == gridDim.x - 1 && lane == 0) {
+            counter[0] = 0;
+            counter[1] = 0;
+        }
+    }
+}
+
+// Measurement only: a plain write of n16 16-byte words of `v`, each
+// workgroup of 256 threads storing 4 KiB pieces, grid-stride.
+template <bool NT>
+__global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint32_t v) {
+    using D = DwordVec<4>::type;
+    const D d = {v, v, v, v};
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * 256) {
+        if constexpr (NT) __builtin_nontemporal_store(d, (VMT_GLOBAL D*)(p + i));
+        else *(VMT_GLOBAL D*)(p + i) = d;
     }
 }
 
@@ -1683,6 +1768,44 @@ hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchS
     if (!kern) return hipErrorInvalidValue;
     void* args[] = {(void*)&d_tasks, (void*)&count, (void*)&d_counter};
     return hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, stream);
+}
+
+template <class P, int LL>
+static const void* pattern_shape_kernel(uint32_t tv, uint32_t sw) {
+    if (tv == 0) return sw == 16 ? reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 0, 16>)
+                                 : reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 0, 8>);
+    if (tv == 1) return sw == 16 ? reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 1, 16>)
+                                 : reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 1, 8>);
+    return sw == 16 ? reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 2, 16>)
+                    : reinterpret_cast<const void*>(write_pattern_kernel<P, LL, 2, 8>);
+}
+
+bool pattern_supported(uint32_t variant, uint32_t M, int out_kind) {
+    return (variant == kMT32 && M == 16 && out_kind == kOutU32) || (variant == kMT64 && M == 8 && out_kind == kOutU64);
+}
+
+hipError_t launch_write_pattern(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape,
+                                const BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream) {
+    if (!pattern_supported(variant, M, out_kind) || !batch_shape_supported(variant, M, out_kind, shape.tv, shape.sw))
+        return hipErrorInvalidValue;
+    uint32_t grid = shape.grid > count ? count : shape.grid;
+    if (grid == 0) return hipSuccess;
+    int threads = 0;
+    (void)batch_kernel_ptr(variant, M, out_kind, shape.tv, shape.sw, &threads);  // same threads as the batch kernel
+    const void* kern = variant == kMT32 ? pattern_shape_kernel<MT32P, 16>(shape.tv, shape.sw)
+                                        : pattern_shape_kernel<MT64P, 8>(shape.tv, shape.sw);
+    void* args[] = {(void*)&d_tasks, (void*)&count, (void*)&d_counter};
+    return hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, stream);
+}
+
+hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t cus, hipStream_t stream) {
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    uint64_t grid = (n16 + 255) / 256;
+    if (grid > (uint64_t)cus * 16) grid = (uint64_t)cus * 16;
+    if (nontemporal) fill_kernel<true><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
+    else fill_kernel<false><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
+    return hipGetLastError();
 }
 
 }  // namespace vmt

@@ -86,6 +86,16 @@ hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int o
 hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
                              uint32_t count, hipStream_t stream);
 
+// Measurement only. launch_write_pattern: the batch kernel's memory traffic
+// for the same tasks and shape without the twist (states unchanged;
+// V-MT19937-32 M = 16 and V-MT19937-64 M = 8 integer outputs).
+// launch_fill: a plain write of `bytes` (a multiple of 16) with 16-byte
+// stores, optionally nontemporal.
+bool pattern_supported(uint32_t variant, uint32_t M, int out_kind);
+hipError_t launch_write_pattern(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape,
+                                const BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream);
+hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t cus, hipStream_t stream);
+
 // Copy states: task i copies tasks[i].src to tasks[i].dst (bytes, a multiple of 16).
 hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream);
 

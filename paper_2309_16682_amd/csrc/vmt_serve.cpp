@@ -164,8 +164,13 @@ vmt_server* vmt_server_create(vmt_ctx* ctx, void* const* d_states, size_t n_stat
         if (status) *status = c;
         return nullptr;
     };
-    if (!ctx || vmt::ctx_device(ctx) < 0) return fail(VMT_EDEVICE, "server needs a device context");
+    if (!ctx) return fail(VMT_EINVAL, "null context");
     if (!d_states || n_states == 0 || !d_arena || arena_bytes == 0) return fail(VMT_EINVAL, "empty states or arena");
+    if (vmt::reject_duplicate_states(d_states, n_states)) {  // two requests could then run one state at once
+        if (status) *status = VMT_EINVAL;
+        return nullptr;
+    }
+    if (vmt::ctx_device(ctx) < 0) return fail(VMT_EDEVICE, "server needs a device context");
     if (n_streams < 1 || n_streams > 16) return fail(VMT_EINVAL, "1 <= streams <= 16");
     if (mode < 0 || mode > 7) return fail(VMT_EINVAL, "mode: bit 0 plain launches, bit 1 retain outputs, bit 2 split");
     if ((mode & 1) && (mode & 4)) return fail(VMT_EINVAL, "the plain form does not split requests");

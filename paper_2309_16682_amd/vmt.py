@@ -14,8 +14,7 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-# VMT_LIBRARY may name another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("VMT_LIBRARY") or os.path.join(PKG, "libvmt.so")
+LIB_PATH = os.path.join(PKG, "libvmt.so")
 
 VMT_OK = 0
 VMT_EINVAL, VMT_EVARIANT, VMT_ENOMEM, VMT_EDEVICE, VMT_EBUSY, VMT_ESTATE = -1, -2, -3, -4, -5, -6
@@ -73,6 +72,8 @@ def lib():
         "vmt_batch_plan_create": ([P, P, P, P, SZ, I, IP], P),
         "vmt_batch_plan_launch": ([P, P], I),
         "vmt_batch_plan_destroy": ([P], I),
+        "vmt_batch_plan_write_pattern": ([P, P], I),
+        "vmt_calib_fill": ([P, P, SZ, I, P], I),
         "vmt_state_export": ([P, P, P, SZ, P], I),
         "vmt_state_import": ([P, P, P, SZ, P], I),
         "vmt_state_release": ([P, P], I),
@@ -102,6 +103,7 @@ def exported_symbols() -> list:
         "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
         "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
+        "vmt_batch_plan_write_pattern", "vmt_calib_fill",
         "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_check_poly",
         "vmt_check_stream", "vmt_shape_get", "vmt_shape_set", "vmt_autotune",
         "vmt_server_create", "vmt_server_run", "vmt_server_destroy", "vmt_server_set_watchdog",
@@ -247,6 +249,15 @@ def vmt_batch_plan_launch(plan, stream=None):
 
 def vmt_batch_plan_destroy(plan):
     return _check(lib().vmt_batch_plan_destroy(plan))
+
+
+def vmt_batch_plan_write_pattern(plan, stream=None):
+    return _check(lib().vmt_batch_plan_write_pattern(plan, _stream(stream)))
+
+
+def vmt_calib_fill(ctx, d_buf, nbytes=None, nontemporal=False, stream=None):
+    n = d_buf.numel() * d_buf.element_size() if nbytes is None else nbytes
+    return _check(lib().vmt_calib_fill(ctx, _dptr(d_buf), n, 1 if nontemporal else 0, _stream(stream)))
 
 
 def vmt_state_export(ctx, d_state, stream=None) -> np.ndarray:

@@ -27,6 +27,21 @@ def test_library_exports_every_declared_symbol():
     assert set(vmt.exported_symbols()) == set(names)
 
 
+def test_every_declaration_cites_its_passage():
+    # each declaration's comment names the passage of the paper that defines
+    # the operation, or says that the paper is silent on it
+    text = open(os.path.join(ROOT, "include", "vmt.h")).read()
+    lines = text.split("\n")
+    for name in declared_functions():
+        k = next(i for i, l in enumerate(lines) if re.match(r"^[a-z].*\b" + name + r"\s*\(", l))
+        end = max(i for i in range(k) if "*/" in lines[i])
+        start = max(i for i in range(end + 1) if lines[i].lstrip().startswith("/*"))
+        block = " ".join(lines[start : end + 1])
+        assert "Cite:" in block, name
+        cite = block[block.index("Cite:"):]
+        assert re.search(r"Sec\. \d|eq\. \(|paper silent|as vmt_", cite), name
+
+
 def test_host_only_context_and_error_paths():
     from paper_2309_16682_amd import vmt
 
@@ -43,9 +58,13 @@ def test_host_only_context_and_error_paths():
         r = vmt.lib().vmt_init_genrand(ctx, 0, 1, 4, ctypes.c_void_p(256), None)
         assert r == vmt.VMT_EDEVICE
         assert b"host-only" in vmt.lib().vmt_last_error()
-        # a server needs a device; the server calls reject null handles
+        # a server needs states, an arena and a device; the server calls reject null handles
         st = ctypes.c_int(0)
         assert not vmt.lib().vmt_server_create(ctx, None, 0, None, 0, 0, 0, 1, 0, 0, ctypes.byref(st))
+        assert st.value == vmt.VMT_EINVAL
+        two = (ctypes.c_void_p * 2)(256, 512)
+        assert not vmt.lib().vmt_server_create(ctx, two, 2, ctypes.c_void_p(4096), 4096, 4096, 0, 1, 0, 0,
+                                               ctypes.byref(st))
         assert st.value == vmt.VMT_EDEVICE
         assert vmt.lib().vmt_server_set_watchdog(None, 1.0) == vmt.VMT_EINVAL
         assert vmt.lib().vmt_server_destroy(None) == vmt.VMT_EINVAL
@@ -105,5 +124,35 @@ def test_library_jump_poly_lane_distances_match_oracle_fixtures():
             J = 1 << (golden_io.MEXP[variant] - 4)
             ref = O.poly_mulmod(golden_io.lane_poly(variant, 16), O.poly_powmod_t(d, mu), mu)
             assert vmt.vmt_jump_poly(ctx, variant, J + d) == ref, variant
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
+
+
+def test_calls_on_several_states_reject_a_state_given_twice():
+    # two workgroups seeding, jumping or serving one window in place at once would race: every call that
+    # takes a list of states rejects a repeated pointer before it touches the device
+    from paper_2309_16682_amd import vmt
+
+    L = vmt.lib()
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        dup = (ctypes.c_void_p * 3)(256, 512, 256)
+        keys = (ctypes.c_uint32 * 12)(*range(12))
+        ks = (ctypes.c_uint32 * 3)(40, 41, 42)
+        lens = (ctypes.c_uint64 * 3)(1, 1, 1)
+        outs = (ctypes.c_void_p * 3)(4096, 8192, 12288)
+        assert L.vmt_init_by_array_batch(ctx, keys, 4, 3, 16, dup, None) == vmt.VMT_EINVAL
+        assert b"twice" in L.vmt_last_error()
+        assert L.vmt_jump_pow2_batch(ctx, dup, ks, 3, None) == vmt.VMT_EINVAL
+        assert b"twice" in L.vmt_last_error()
+        st = ctypes.c_int(0)
+        assert not L.vmt_server_create(ctx, dup, 3, ctypes.c_void_p(4096), 4096, 4096, 0, 1, 0, 0, ctypes.byref(st))
+        assert st.value == vmt.VMT_EINVAL and b"twice" in L.vmt_last_error()
+        # the same lists without the repeat get as far as the device check
+        ok = (ctypes.c_void_p * 3)(256, 512, 768)
+        assert L.vmt_init_by_array_batch(ctx, keys, 4, 3, 16, ok, None) == vmt.VMT_EDEVICE
+        assert L.vmt_jump_pow2_batch(ctx, ok, ks, 3, None) == vmt.VMT_EDEVICE
+        # vmt_batch_generate checks registration first; unknown states are a state error, never a race
+        assert L.vmt_batch_generate(ctx, dup, lens, outs, 3, 0, None) in (vmt.VMT_EDEVICE, vmt.VMT_ESTATE)
     finally:
         vmt.vmt_ctx_destroy(ctx)
