@@ -27,7 +27,8 @@
  *   - Allocation: batched calls, split generation and jumps allocate their
  *     task lists (and split generation its scratch copies of the state)
  *     stream-ordered (hipMallocAsync on the call's stream); plans and servers
- *     allocate once, at creation.
+ *     allocate once, at creation. vmt_batch_generate_noalloc allocates
+ *     nothing (its task list goes into a fixed device scratch array).
  *   - Concurrency: calls on different states may overlap on different
  *     streams. Calls on one state must be ordered by the caller (one stream).
  *
@@ -201,6 +202,28 @@ int vmt_uniform_f64(vmt_ctx* ctx, void* d_state, size_t n, double* d_out, hipStr
  */
 int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
                        size_t count, int out_kind, hipStream_t stream);
+
+/* Allocation-free form of vmt_batch_generate: same arguments, same results,
+ * same kernels, but the task list and the work-queue counters go into a
+ * fixed scratch array in device memory (a file-scope array of the library,
+ * one per GPU, held until the process ends) instead of memory allocated per
+ * call. The call itself allocates no device memory: no hipMalloc, hipFree or
+ * stream-ordered allocation. The host task list is copied in with
+ * hipMemcpyAsync on `stream`. At most VMT_NOALLOC_MAX_TASKS states per call
+ * (VMT_EINVAL beyond, nothing enqueued). The scratch array of a GPU is
+ * shared by every call of this function on that GPU and keeps the last
+ * call's task list: calls that overlap on one GPU (on different streams, or
+ * from different threads without ordering) race and may produce wrong
+ * outputs; the caller orders them, e.g. on one stream. The context must have
+ * been created for a device (vmt_ctx_create looks the array's device address
+ * up then, once per GPU).
+ * Cite: for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it);
+ * the operation is vmt_batch_generate's.
+ */
+#define VMT_NOALLOC_MAX_TASKS 32768
+int vmt_batch_generate_noalloc(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
+                               size_t count, int out_kind, hipStream_t stream);
 
 /* Plan form of vmt_batch_generate for repeated replay: uploads the task list
  * once and returns a handle whose launch reuses it (the same states, lengths

@@ -683,6 +683,12 @@ vmt_ctx* vmt_ctx_create(int device, int* status) {
             if (status) *status = hip_fail(e, "hipSetDevice");
             return nullptr;
         }
+        // the device address of the allocation-free call's scratch array, looked up once per device
+        e = vmt::noalloc_scratch_init(device);
+        if (e != hipSuccess) {
+            if (status) *status = hip_fail(e, "scratch array address");
+            return nullptr;
+        }
     }
     if (status) *status = VMT_OK;
     return ctx.release();
@@ -883,6 +889,35 @@ int vmt_batch_generate(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens
     }
     (void)hipFreeAsync(d_buf, stream);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return VMT_OK;
+}
+
+static_assert(VMT_NOALLOC_MAX_TASKS == vmt::kNoAllocMaxTasks, "header and library agree on the scratch size");
+
+int vmt_batch_generate_noalloc(vmt_ctx* ctx, void* const* d_states, const uint64_t* lens, void* const* d_outs,
+                               size_t count, int out_kind, hipStream_t stream) {
+    if (!ctx) return fail(VMT_EINVAL, "null context");
+    if (count > VMT_NOALLOC_MAX_TASKS)
+        return fail(VMT_EINVAL, "%zu states in one allocation-free batch call; at most %u", count,
+                    (unsigned)VMT_NOALLOC_MAX_TASKS);
+    int st = set_device(ctx);
+    if (st) return st;
+    StateInfo info{};
+    st = validate_batch_args(ctx, d_states, lens, d_outs, count, out_kind, &info);
+    if (st || count == 0) return st;
+    vmt::BatchTask* d_tasks = nullptr;
+    uint32_t* d_counter = nullptr;
+    hipError_t e = vmt::noalloc_scratch(ctx->device, &d_tasks, &d_counter);
+    if (e != hipSuccess) return hip_fail(e, "scratch array");
+    std::vector<vmt::BatchTask> tasks = batch_tasks(d_states, lens, d_outs, count);
+    e = hipMemcpyAsync(d_tasks, tasks.data(), count * sizeof(vmt::BatchTask), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = vmt::reset_counters(d_counter, stream);  // a kernel, not a memset
+    if (e == hipSuccess) {
+        vmt::BatchShape shape;
+        if (!vmt::is_sfmt(info.variant)) vmt::ctx_batch_shape(ctx, info.variant, info.M, out_kind, &shape);
+        e = launch_tasks(info.variant, info.M, out_kind, shape, d_tasks, (uint32_t)count, d_counter, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "allocation-free batch launch");
     return VMT_OK;
 }
 

@@ -37,6 +37,7 @@
 // within a row of 16 (sfmt_quad_thread).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "vmt_common.hpp"
@@ -1261,6 +1262,7 @@ __global__ __launch_bounds__(G * 64) void init_kernel(const InitTask* tasks, Ini
         h->word_bytes = sizeof(W);
         h->block = (uint32_t)(N * M * (sizeof(W) == 16 ? 4 : 1));
         h->pos = 0;
+        for (int i = 0; i < (int)(sizeof(h->reserved) / sizeof(h->reserved[0])); ++i) h->reserved[i] = 0;
     }
 }
 
@@ -1806,6 +1808,55 @@ hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t c
     if (nontemporal) fill_kernel<true><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
     else fill_kernel<false><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
     return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free batch call: the task list (up to
+// kNoAllocMaxTasks entries) and the queue's two counters, in one file-scope
+// device array. In host code `scratch` names a host-side stand-in, so its
+// device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is ever handed to kernels or
+// copies. Every call on a device shares that device's array.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kNoAllocTaskBytes = (size_t)kNoAllocMaxTasks * sizeof(BatchTask);
+static_assert(kNoAllocTaskBytes % 256 == 0, "the counters start on a 256-byte boundary");
+static __device__ __align__(256) uint8_t scratch[kNoAllocTaskBytes + 256];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current first
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[device] = static_cast<uint8_t*>(ptr);
+    return hipSuccess;
+}
+
+hipError_t noalloc_scratch(int device, BatchTask** d_tasks, uint32_t** d_counter) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    uint8_t* base;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch[device];
+    }
+    if (!base) return hipErrorNotInitialized;
+    *d_tasks = reinterpret_cast<BatchTask*>(base);
+    *d_counter = reinterpret_cast<uint32_t*>(base + kNoAllocTaskBytes);
+    return hipSuccess;
 }
 
 }  // namespace vmt

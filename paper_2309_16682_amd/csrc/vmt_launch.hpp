@@ -96,6 +96,15 @@ hipError_t launch_write_pattern(uint32_t variant, uint32_t M, int out_kind, cons
                                 const BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream);
 hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t cus, hipStream_t stream);
 
+// Allocation-free batch call. The task list and counters live in a
+// file-scope device array of kNoAllocMaxTasks tasks, one per device, shared
+// by every call on that device. noalloc_scratch_init looks its address up for
+// `device` (which must be current) once; noalloc_scratch returns it
+// (hipErrorNotInitialized before init).
+constexpr uint32_t kNoAllocMaxTasks = 32768;
+hipError_t noalloc_scratch_init(int device);
+hipError_t noalloc_scratch(int device, BatchTask** d_tasks, uint32_t** d_counter);
+
 // Copy states: task i copies tasks[i].src to tasks[i].dst (bytes, a multiple of 16).
 hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream);
 

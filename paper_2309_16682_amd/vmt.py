@@ -25,6 +25,7 @@ SFMT_FAMILY = (VMT_SFMT, VMT_SFMT607, VMT_SFMT1279, VMT_SFMT2281, VMT_SFMT4253, 
 MEXP = {VMT_MT32: 19937, VMT_MT64: 19937, VMT_SFMT: 19937, VMT_SFMT607: 607, VMT_SFMT1279: 1279,
         VMT_SFMT2281: 2281, VMT_SFMT4253: 4253, VMT_SFMT11213: 11213}
 VMT_OUT_U32, VMT_OUT_U64, VMT_OUT_F32, VMT_OUT_F64 = 0, 1, 2, 3
+VMT_NOALLOC_MAX_TASKS = 32768
 
 STATE_WORDS = {VMT_MT32: 624, VMT_MT64: 312, **{v: MEXP[v] // 128 + 1 for v in SFMT_FAMILY}}
 
@@ -69,6 +70,7 @@ def lib():
         "vmt_uniform_f32": ([P, P, SZ, P, P], I),
         "vmt_uniform_f64": ([P, P, SZ, P, P], I),
         "vmt_batch_generate": ([P, P, P, P, SZ, I, P], I),
+        "vmt_batch_generate_noalloc": ([P, P, P, P, SZ, I, P], I),
         "vmt_batch_plan_create": ([P, P, P, P, SZ, I, IP], P),
         "vmt_batch_plan_launch": ([P, P], I),
         "vmt_batch_plan_destroy": ([P], I),
@@ -102,7 +104,7 @@ def exported_symbols() -> list:
         "vmt_last_error", "vmt_version", "vmt_ctx_create", "vmt_ctx_destroy", "vmt_state_bytes",
         "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
-        "vmt_batch_generate", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
+        "vmt_batch_generate", "vmt_batch_generate_noalloc", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
         "vmt_batch_plan_write_pattern", "vmt_calib_fill",
         "vmt_state_export", "vmt_state_import", "vmt_state_release", "vmt_minpoly", "vmt_jump_poly", "vmt_check_poly",
         "vmt_check_stream", "vmt_shape_get", "vmt_shape_set", "vmt_autotune",
@@ -228,6 +230,19 @@ def vmt_batch_generate(ctx, d_states, lens, d_outs, out_kind, stream=None):
     ln = np.ascontiguousarray(lens, dtype=np.uint64)
     return _check(
         lib().vmt_batch_generate(ctx, sp, ln.ctypes.data_as(ctypes.c_void_p), op, n, out_kind, _stream(stream))
+    )
+
+
+def vmt_batch_generate_noalloc(ctx, d_states, lens, d_outs, out_kind, stream=None):
+    """vmt_batch_generate with the task list in the library's fixed device
+    scratch array (no device allocation; at most VMT_NOALLOC_MAX_TASKS states)."""
+    n = len(d_states)
+    sp = _ptr_array([s if isinstance(s, int) else s.data_ptr() for s in d_states])
+    op = _ptr_array([o if isinstance(o, int) else o.data_ptr() for o in d_outs])
+    ln = np.ascontiguousarray(lens, dtype=np.uint64)
+    return _check(
+        lib().vmt_batch_generate_noalloc(ctx, sp, ln.ctypes.data_as(ctypes.c_void_p), op, n, out_kind,
+                                         _stream(stream))
     )
 
 

@@ -39,7 +39,7 @@ def test_every_declaration_cites_its_passage():
         block = " ".join(lines[start : end + 1])
         assert "Cite:" in block, name
         cite = block[block.index("Cite:"):]
-        assert re.search(r"Sec\. \d|eq\. \(|paper silent|as vmt_", cite), name
+        assert re.search(r"Sec\. \d|eq\. \(|paper silent|as vmt_|callers that cannot allocate", cite), name
 
 
 def test_host_only_context_and_error_paths():
@@ -154,5 +154,24 @@ def test_calls_on_several_states_reject_a_state_given_twice():
         assert L.vmt_jump_pow2_batch(ctx, ok, ks, 3, None) == vmt.VMT_EDEVICE
         # vmt_batch_generate checks registration first; unknown states are a state error, never a race
         assert L.vmt_batch_generate(ctx, dup, lens, outs, 3, 0, None) in (vmt.VMT_EDEVICE, vmt.VMT_ESTATE)
+    finally:
+        vmt.vmt_ctx_destroy(ctx)
+
+
+def test_noalloc_batch_rejects_oversized_calls_before_the_device():
+    # the allocation-free batch call holds its task list in a fixed scratch array: a larger call is an argument
+    # error, reported before anything is enqueued (here on a host-only context, whose device calls fail otherwise)
+    from paper_2309_16682_amd import vmt
+
+    L = vmt.lib()
+    ctx = vmt.vmt_ctx_create(-1)
+    try:
+        G = vmt.VMT_NOALLOC_MAX_TASKS + 1
+        sp = (ctypes.c_void_p * G)(*[256 * (i + 1) for i in range(G)])
+        lens = (ctypes.c_uint64 * G)(*([1] * G))
+        assert L.vmt_batch_generate_noalloc(ctx, sp, lens, sp, G, 0, None) == vmt.VMT_EINVAL
+        assert b"at most 32768" in L.vmt_last_error()
+        assert L.vmt_batch_generate_noalloc(ctx, sp, lens, sp, 3, 0, None) == vmt.VMT_EDEVICE
+        assert L.vmt_batch_generate_noalloc(None, sp, lens, sp, 3, 0, None) == vmt.VMT_EINVAL
     finally:
         vmt.vmt_ctx_destroy(ctx)
