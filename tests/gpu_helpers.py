@@ -100,3 +100,14 @@ def oracle_map(fn, jobs, workers=8):
         return [fn(j) for j in jobs]
     with multiprocessing.get_context("spawn").Pool(workers) as pool:
         return pool.map(fn, jobs, chunksize=2)
+
+
+def oracle_key_digests(args):
+    """(variant, M, key, segs) -> sha256 hex digests of consecutive segments
+    of the oracle V-stream from init_by_array(key), segs[j] elements each.
+    Top-level for spawned workers; touches neither torch nor the GPU."""
+    import hashlib
+
+    variant, M, key, segs = args
+    ref = oracle_stream(variant, M, key=[int(k) for k in key])
+    return [hashlib.sha256(ref.generate(int(n)).tobytes()).hexdigest() for n in segs]

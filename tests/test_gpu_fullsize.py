@@ -11,6 +11,19 @@ oracle (tolerance 0).
            of 40 more; and every output of the round long enough to check
            (more than 19,937 words) passes the linear-complexity check (each
            bit obeys mu), a property that holds at any size.
+  batched, every round and both steps: the benchmark's step as it times it
+           (same autotuning sample, rounds over the 96 GiB arena, one HIP
+           graph holding every round's launch) replayed twice, the second
+           replay continuing every stream; the graph also copies the outputs
+           of 1,024 sampled generators (the longest and shortest of each round
+           and random ones in proportion to the rounds) out of the arena after
+           their round, and each is compared in full with the oracle (sha256 of
+           all its elements of both steps; a mismatch is then located element
+           by element).
+  single streams: workloads 1-3 at the launch shape the benchmark's
+           autotuning picks (lanes per workgroup, chunk length), two calls in
+           a row on one state as the benchmark times them, every element of
+           both calls against the oracle.
   serving: 4,096 V-MT19937-64 (M = 8) states, the benchmark's trace (Poisson
            20k/s, 4 KiB - 256 MiB, 10 % jumps by 2^k) for its first 0.25 s,
            long requests split by jump-ahead, outputs retained; every request
@@ -20,7 +33,7 @@ oracle (tolerance 0).
 import numpy as np
 import pytest
 
-from tests.gpu_helpers import as_u, oracle_stream, pow2_poly, say
+from tests.gpu_helpers import as_u, oracle_key_digests, oracle_stream, pow2_poly, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -95,6 +108,136 @@ def test_batched_workload_first_round(ctx):
     bad = torch.nonzero(cnt).flatten().cpu().numpy()
     assert len(checked) > 0.5 * len(idx)
     assert bad.size == 0, [(checked[j], int(cnt[j])) for j in bad[:5]]
+
+
+def test_batched_workload_every_round_both_steps(ctx):
+    import hashlib
+    import multiprocessing
+
+    G, M, kind = 65536, 16, vmt.VMT_OUT_U32
+    keys = batch_keys(G, seed=42)
+    lens = batch_lengths(G, seed=43)
+    sb = vmt.vmt_state_bytes(MT32, M)
+    pool = torch.empty(G * sb, dtype=torch.uint8, device="cuda")
+    states = [pool[i * sb : (i + 1) * sb] for i in range(G)]
+    vmt.vmt_init_by_array_batch(ctx, keys, M, states)
+    tune_lens = np.random.default_rng(17).choice(lens, size=8192, replace=False)  # the benchmark's sample
+    vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_BATCH, MT32, M, kind, tune_lens, reps=2)
+    shape = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_BATCH, MT32, M, kind)
+    free, _ = torch.cuda.mem_get_info()
+    arena_bytes = max(int(min(96 * 2**30, free - 16 * 2**30)), 1 << 30)
+    rounds, offs = plan_rounds(lens, arena_bytes, 4)
+    rng = np.random.default_rng(4)
+    sample = []
+    for idx in rounds:
+        idx = np.asarray(idx)
+        by = idx[np.argsort(lens[idx], kind="stable")]
+        pick = {int(i) for i in list(by[:4]) + list(by[-4:])}
+        want = -(-1032 * len(idx) // G)
+        rest = [int(i) for i in rng.permutation(idx) if int(i) not in pick][: max(0, want - len(pick))]
+        sample.append(sorted(pick | set(rest)))
+    flat = [i for r in sample for i in r]
+    assert len(flat) >= 1024 and len(set(flat)) == len(flat)
+    say(f"case batched every round: {len(rounds)} rounds, shape {shape.threads} threads / {shape.store_bytes} B stores / "
+        f"{shape.wg_per_cu} per CU, {len(flat)} sampled generators")
+    # the oracle's digests run on CPU workers while the GPU works
+    jobs = [(MT32, M, tuple(int(x) for x in keys[i]), (int(lens[i]), int(lens[i]))) for i in flat]
+    workers = max(1, min(16, multiprocessing.cpu_count()))
+    pool_cpu = multiprocessing.get_context("spawn").Pool(workers)
+    try:
+        pending = pool_cpu.map_async(oracle_key_digests, jobs, chunksize=4)
+        co, tot = {}, 0
+        for i in flat:
+            co[i] = tot
+            tot += (4 * int(lens[i]) + 255) // 256 * 256
+        arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        chk = torch.empty(tot, dtype=torch.uint8, device="cuda")
+        base = arena.data_ptr()
+        plans = [vmt.vmt_batch_plan_create(ctx, [states[int(i)].data_ptr() for i in idx],
+                                           [int(lens[i]) for i in idx], [base + offs[int(i)] for i in idx], kind)
+                 for idx in rounds]
+        host = []
+        try:
+            side = torch.cuda.Stream()
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    for r, p in enumerate(plans):
+                        vmt.vmt_batch_plan_launch(p)
+                        for i in sample[r]:
+                            n4 = 4 * int(lens[i])
+                            chk[co[i] : co[i] + n4].copy_(arena[offs[i] : offs[i] + n4])
+            for step in range(2):
+                say(f"case batched every round: replay {step + 1}")
+                chk.fill_(0)
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                host.append(chk.cpu().numpy())
+        finally:
+            torch.cuda.synchronize()
+            for p in plans:
+                vmt.vmt_batch_plan_destroy(p)
+        del arena, chk
+        say("case batched every round: waiting for the oracle")
+        digests = pending.get(timeout=240)
+    finally:
+        pool_cpu.terminate()
+    for j, i in enumerate(flat):
+        n = int(lens[i])
+        for step in range(2):
+            seg = host[step][co[i] : co[i] + 4 * n]
+            if hashlib.sha256(seg.tobytes()).hexdigest() != digests[j][step]:
+                ref = oracle_stream(MT32, M, key=keys[i]).generate(2 * n)[step * n : (step + 1) * n]
+                np.testing.assert_array_equal(seg.view(np.uint32), ref, err_msg=f"generator {i} step {step + 1}")
+                raise AssertionError(f"generator {i} step {step + 1}: digest differs")
+
+
+# the benchmark's single-stream configurations: name, variant, M, seed, elements, output kind
+SINGLE = [
+    ("mt32_M16_2^24_u32", MT32, 16, 5489, 1 << 24, "u32"),
+    ("mt32_M1_2^24_u32", MT32, 1, 5489, 1 << 24, "u32"),
+    ("mt64_M8_2^26_u64", MT64, 8, 5489, 1 << 26, "u64"),
+    ("mt64_M8_2^26_f64", MT64, 8, 5489, 1 << 26, "f64"),
+    ("sfmt_M4_2^28_u32", vmt.VMT_SFMT, 4, 1234, 1 << 28, "u32"),
+    ("sfmt_M64_2^28_u32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "u32"),
+    ("sfmt_M64_2^28_f32", vmt.VMT_SFMT, 64, 1234, 1 << 28, "f32"),
+    ("sfmt607_M64_2^28_u32", vmt.VMT_SFMT607, 64, 1234, 1 << 28, "u32"),
+    ("sfmt11213_M16_2^28_u32", vmt.VMT_SFMT11213, 16, 1234, 1 << 28, "u32"),
+]
+
+
+@pytest.mark.parametrize("name,variant,M,seed,n,kind", SINGLE, ids=[c[0] for c in SINGLE])
+def test_single_stream_at_the_autotuned_shape(ctx, name, variant, M, seed, n, kind):
+    from oracle import pyoracle as O
+
+    okind = {"u32": vmt.VMT_OUT_U32, "u64": vmt.VMT_OUT_U64, "f64": vmt.VMT_OUT_F64, "f32": vmt.VMT_OUT_F32}[kind]
+    best, _ = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind, [n], reps=2)
+    say(f"case single stream {name}: {best.lanes_per_wg} lanes per workgroup, split 2^{best.split_log2}")
+    try:
+        st = vmt.new_state(variant, M)
+        vmt.vmt_init_genrand(ctx, variant, seed, M, st)
+        esz = 8 if kind in ("u64", "f64") else 4
+        fn = {"u32": vmt.vmt_generate_u32, "u64": vmt.vmt_generate_u64, "f64": vmt.vmt_uniform_f64,
+              "f32": vmt.vmt_uniform_f32}[kind]
+        ref = oracle_stream(variant, M, seed=seed)
+        for call in range(2):
+            out = torch.empty(n * esz, dtype=torch.uint8, device="cuda")
+            fn(ctx, st, n, out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            del out
+            r = ref.generate(n)
+            if kind == "f64":
+                exp = O.map_f64(r)
+            elif kind == "f32":
+                exp = O.map_f32(r)
+            else:
+                exp = r
+            np.testing.assert_array_equal(got.view(exp.dtype), exp, err_msg=f"{name} call {call + 1}")
+    finally:
+        vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind)
 
 
 def test_serving_workload_sampled(ctx):
