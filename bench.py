@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving section only")
     ap.add_argument("--only-check", action="store_true", help="run the linear-complexity self-check section only")
+    ap.add_argument("--only-variants", type=str, default=None,
+                    help="run these batched family lines only (comma-separated names, e.g. mt64_M8_u64, or 'all')")
     ap.add_argument("--only-single", type=str, default=None,
                     help="run these single-stream configurations only (comma-separated names, e.g. sfmt_M4_2^28_u32)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
@@ -272,26 +274,112 @@ def single_streams(ctx, torch, args, only=None) -> dict:
         st = vmt.new_state(variant, M)
         vmt.vmt_init_genrand(ctx, variant, seed, M, st)
         esz = 8 if kind in ("u64", "f64") else 4
-        out = torch.empty(n * esz, dtype=torch.uint8, device=dev)
+        # successive calls write to a rotation of output buffers totalling at least 1 GiB, so that no call's
+        # output still sits in the 256 MB last-level cache when the next one is timed
+        nbuf = max(2, -(-(1 << 30) // (n * esz)))
+        outs = [torch.empty(n * esz, dtype=torch.uint8, device=dev) for _ in range(nbuf)]
         fn = {"u32": vmt.vmt_generate_u32, "u64": vmt.vmt_generate_u64, "f64": vmt.vmt_uniform_f64,
               "f32": vmt.vmt_uniform_f32}[kind]
-        fn(ctx, st, n, out)
+        fn(ctx, st, n, outs[-1])
         torch.cuda.synchronize()
-        reps = 2 if variant in vmt.SFMT_FAMILY and M <= 16 else 3
+        reps = max(nbuf, 2 if variant in vmt.SFMT_FAMILY and M <= 16 else 3)
         e0.record()
-        for _ in range(reps):
-            fn(ctx, st, n, out)
+        for r in range(reps):
+            fn(ctx, st, n, outs[r % nbuf])
         e1.record()
         torch.cuda.synchronize()
         s = e0.elapsed_time(e1) * 1e-3 / reps
         shp = vmt.vmt_shape_get(ctx, vmt.VMT_FAMILY_GENERATE, variant, M, okind)
-        sec[name] = {"GB/s": round(n * esz / s / 1e9, 2), "ms": round(s * 1e3, 3),
+        gbps = n * esz / s / 1e9
+        sec[name] = {"GB/s": round(gbps, 2), "ms": round(s * 1e3, 3),
                      "lanes_per_wg": shp.lanes_per_wg,
                      "split": "never" if shp.split_log2 == 255 else (
-                         "auto" if shp.split_log2 == 0 else f"chunks of 2^{shp.split_log2} lane steps")}
+                         "auto" if shp.split_log2 == 0 else f"chunks of 2^{shp.split_log2} lane steps"),
+                     "output_rotation": f"{nbuf} buffers, {nbuf * n * esz / 2**30:.2f} GiB",
+                     # whole call (copies, jumps, generation, position fix-ups) against the HBM write peak
+                     "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbps / HBM_PEAK_GBS, 4), "scope": "whole call, output bytes"}}
         log(f"{name}: {sec[name]}")
-        del out
+        del outs
     return sec
+
+
+# Batched lines of the other generator families: 65,536 lanes' worth of generators (65,536 / M of them) seeded
+# init_genrand(i + 1) in one batched call, each asked for a log-uniform number of elements in
+# [M/16 * 1e3, M/16 * 1e7) (the headline batch's volume per lane), one launch of a batch plan over them.
+# name, variant, lanes, output kind, bytes per element
+BATCH_VARIANTS = (
+    ("mt64_M8_u64", 1, 8, 1, 8),
+    ("mt64_M8_f64", 1, 8, 3, 8),
+    ("sfmt_M4_u32", 2, 4, 0, 4),
+    ("sfmt_M4_f32", 2, 4, 2, 4),
+    ("sfmt_M64_u32", 2, 64, 0, 4),
+    ("sfmt_M64_f32", 2, 64, 2, 4),
+)
+
+
+def batched_variants(ctx, torch, args, only=None) -> dict:
+    """Output GB/s and roofline of one batch-plan launch per family (mean of
+    `reps` launches timed with HIP events on the stream they run on; the
+    states continue from launch to launch, the outputs are overwritten)."""
+    from paper_2309_16682_amd import vmt
+    from paper_2309_16682_amd.workload import batch_lengths
+
+    res = {}
+    run_stream = torch.cuda.Stream()
+    for name, variant, M, kind, esz in BATCH_VARIANTS:
+        if only and name not in only:
+            continue
+        G = 65536 // M
+        lens = batch_lengths(G, seed=47, lo=1e3 * M / 16, hi=1e7 * M / 16)
+        sb = vmt.vmt_state_bytes(variant, M)
+        pool = torch.empty(G * sb, dtype=torch.uint8, device="cuda")
+        states = [pool[i * sb : (i + 1) * sb] for i in range(G)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vmt.vmt_init_genrand_batch(ctx, variant, [i + 1 for i in range(G)], M, states)
+        e1.record()
+        torch.cuda.synchronize()
+        init_ms = e0.elapsed_time(e1)
+        tune = None
+        if variant not in vmt.SFMT_FAMILY and not args.no_autotune:  # the MT persistent kernel has launch shapes
+            sample = np.random.default_rng(17).choice(lens, size=min(4096, G), replace=False)
+            best, _ = vmt.vmt_autotune(ctx, vmt.VMT_FAMILY_BATCH, variant, M, kind, sample, reps=2)
+            tune = {"threads": best.threads, "store_bytes": best.store_bytes, "wg_per_cu": best.wg_per_cu}
+        offs = np.concatenate([[0], np.cumsum((lens * esz + 255) // 256 * 256)]).astype(np.int64)
+        arena = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+        plan = vmt.vmt_batch_plan_create(ctx, states, [int(x) for x in lens],
+                                         [arena.data_ptr() + int(o) for o in offs[:-1]], kind)
+        try:
+            with torch.cuda.stream(run_stream):
+                vmt.vmt_batch_plan_launch(plan, run_stream)
+            torch.cuda.synchronize()
+            reps = 3
+            e0.record(run_stream)
+            for _ in range(reps):
+                vmt.vmt_batch_plan_launch(plan, run_stream)
+            e1.record(run_stream)
+            torch.cuda.synchronize()
+        finally:
+            vmt.vmt_batch_plan_destroy(plan)
+        ms = e0.elapsed_time(e1) / reps
+        out_bytes = int(lens.sum()) * esz
+        alg = out_bytes + 2 * (sb - 256) * G
+        res[name] = {
+            "generators": G, "lanes": M, "elements": int(lens.sum()), "output_bytes": out_bytes,
+            "lengths": f"log-uniform [{1e3 * M / 16:g}, {1e7 * M / 16:g}) elements (splitmix64(47))",
+            "seeding": f"init_genrand(i + 1), one batched call: {init_ms:.1f} ms",
+            "ms_per_launch": round(ms, 3), "GB/s": round(out_bytes / (ms * 1e-3) / 1e9, 1),
+            "shape": tune,
+            "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_launch": alg,
+                         "kernel": ("batch_mt_kernel" if variant == 1 else "batch_sfmt_kernel")},
+        }
+        log(f"batched {name}: {res[name]}")
+        del arena, pool, states
+        torch.cuda.empty_cache()
+    return res
 
 
 def call_size_sweep(ctx, torch) -> dict:
@@ -369,7 +457,8 @@ def self_check(ctx, torch, reps: int = 3) -> dict:
     return res
 
 
-def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chunk: int = 1 << 20) -> dict:
+def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chunk: int = 1 << 20,
+            rate: float = 20000.0) -> dict:
     """Serving configuration: 4096 device-resident V-MT19937-64 (M = 8)
     states seeded init_genrand(i + 1); Poisson arrivals at 20k requests/s,
     request sizes log-uniform in [4 KiB, 256 MiB] of uint64, 10% of requests
@@ -384,12 +473,11 @@ def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chu
     sb = vmt.vmt_state_bytes(vmt.VMT_MT64, Mv)
     pool = torch.empty(n_states * sb, dtype=torch.uint8, device="cuda")
     states = [pool[i * sb : (i + 1) * sb] for i in range(n_states)]
-    for i, st in enumerate(states):
-        vmt.vmt_init_genrand(ctx, vmt.VMT_MT64, i + 1, Mv, st)
+    vmt.vmt_init_genrand_batch(ctx, vmt.VMT_MT64, [i + 1 for i in range(n_states)], Mv, states)
     torch.cuda.synchronize()
     budget = 16 * 2**30
     arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
-    trace = serving_trace(seconds + warm, rate_per_s=20000.0, n_states=n_states, min_bytes=4096,
+    trace = serving_trace(seconds + warm, rate_per_s=rate, n_states=n_states, min_bytes=4096,
                           max_bytes=256 << 20, elem_bytes=8, jump_fraction=0.1, kmin=32, kmax=256, seed=11)
     reqs = [(r.t_arrival, r.state, 0 if r.kind == "gen" else 1, r.nelem if r.kind == "gen" else 0, r.k) for r in trace]
     srv = vmt.vmt_server_create(ctx, states, arena, budget, budget, vmt.VMT_OUT_U64, n_streams=n_streams, mode=mode,
@@ -409,7 +497,10 @@ def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chu
     j = counted & (kind == 1)
     gen_bytes = float((cnt[g] * 8).sum())
     span = float(res["t_done"][counted].max() - warm)
+    offered = float(sum(8 * r[3] for r in reqs if r[0] >= warm)) / seconds
     out = {
+        "offered_requests_per_s": rate,
+        "offered_GB/s": round(offered / 1e9, 2),
         "mode": {0: "continuous batching, long requests as successive bounded tasks",
                  4: "continuous batching, long requests split by jump-ahead into chunks run side by side",
                  1: "plain (one launch per request)"}[mode] if chunk else (
@@ -431,6 +522,37 @@ def serving(ctx, seconds: float, warm: float, mode: int, n_streams: int = 4, chu
     }
     del arena, pool
     torch.cuda.empty_cache()
+    return out
+
+
+def serving_capacity(ctx, seconds: float = 2.0, warm: float = 0.5) -> dict:
+    """The serving workload at rising arrival rates (same request mix): a rate
+    is sustained when the loop completes requests at >= 97 % of the offered
+    rate and the p99 wait for admission stays under 50 ms. The capacity is the
+    highest sustained rate, with its delivered GB/s as a fraction of 8 TB/s."""
+    out = {}
+    for label, mode, chunk, rates in (("batched_split", 4, 1 << 20, (20e3, 40e3, 80e3, 160e3, 320e3)),
+                                      ("plain", 1, 0, (500.0, 1e3, 2e3, 4e3))):
+        rows = []
+        for rate in rates:
+            r = serving(ctx, seconds, warm, mode, chunk=chunk, rate=rate)
+            r["sustained"] = bool(r["requests_per_s"] >= 0.97 * rate and r["admit_wait_p99_ms"] < 50.0)
+            rows.append({k: r[k] for k in ("offered_requests_per_s", "offered_GB/s", "requests_per_s", "GB/s",
+                                           "p50_ms", "p99_ms", "jump_p99_ms", "admit_wait_p99_ms", "sustained")})
+            log(f"serving capacity {label} at {rate:g} req/s: {rows[-1]}")
+            if not r["sustained"]:
+                break
+        ok = [x for x in rows if x["sustained"]]
+        best = max(ok, key=lambda x: x["GB/s"]) if ok else None
+        out[label] = {"rates": rows,
+                      "capacity_requests_per_s": best["requests_per_s"] if best else None,
+                      "capacity_GB/s": best["GB/s"] if best else None,
+                      "capacity_frac_of_hbm": round(best["GB/s"] / HBM_PEAK_GBS, 4) if best else None,
+                      "p50_ms_at_capacity": best["p50_ms"] if best else None,
+                      "p99_ms_at_capacity": best["p99_ms"] if best else None}
+    out["rule"] = ("sustained: completed requests/s >= 0.97 x offered and admission-wait p99 < 50 ms; "
+                   f"{seconds:g} s per rate after {warm:g} s warm-up; the sweep of a mode stops at its first "
+                   "unsustained rate")
     return out
 
 
@@ -463,6 +585,12 @@ def main():
                           "call_size_sweep_mt32_M16": call_size_sweep(ctx, torch)}), flush=True)
         vmt.vmt_ctx_destroy(ctx)
         return
+    if args.only_variants:
+        ctx = vmt.vmt_ctx_create(0)
+        only = None if args.only_variants == "all" else args.only_variants.split(",")
+        print(json.dumps({"batched_variants": batched_variants(ctx, torch, args, only)}), flush=True)
+        vmt.vmt_ctx_destroy(ctx)
+        return
     if args.only_check:
         ctx = vmt.vmt_ctx_create(0)
         print(json.dumps({"self_check": self_check(ctx, torch)}), flush=True)
@@ -472,6 +600,7 @@ def main():
         ctx = vmt.vmt_ctx_create(0)
         out = {m: serving(ctx, args.serve_seconds, 1.0, mode, chunk=c) for m, mode, c in
                (("batched_split", 4, 1 << 20), ("batched", 0, 1 << 20), ("batched_unchunked", 0, 0))}
+        out["capacity"] = serving_capacity(ctx)
         print(json.dumps({"serving": out}), flush=True)
         return
     stream = torch.cuda.current_stream()
@@ -696,6 +825,8 @@ def main():
 
     arena = out_base = None  # the batch arena is not needed any more
     torch.cuda.empty_cache()
+    if not args.skip_secondary:
+        result["batched_variants"] = batched_variants(ctx, torch, args)
     if not args.skip_serving:
         result["serving"] = {
             "config": "4096 V-MT19937-64 (M=8) states, Poisson 20k req/s, log-uniform 4 KiB-256 MiB uint64, "
@@ -707,6 +838,7 @@ def main():
             # the plain form cannot keep up with the offered rate: a shorter trace keeps its run bounded
             "plain": serving(ctx, max(args.serve_seconds / 10, 0.5), 0.2, 1, chunk=0),
         }
+        result["serving"]["capacity"] = serving_capacity(ctx)
         log(f"serving: {result['serving']}")
 
     result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, max(1, min(os.cpu_count() or 1, args.cpu_threads)))

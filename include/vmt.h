@@ -136,6 +136,16 @@ int vmt_init_genrand(vmt_ctx* ctx, int variant, uint64_t seed, uint32_t M, void*
 int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key_len, uint32_t M,
                       void* d_state, hipStream_t stream);
 
+/* Batched vmt_init_genrand: count states of one variant with M lanes, state
+ * i seeded init_genrand(seeds[i]) (host array of count seeds); d_states is a
+ * host array of count device pointers (256-byte aligned), each state at most
+ * once (VMT_EINVAL otherwise). One launch seeds and de-phases every lane of
+ * every state; the result equals count vmt_init_genrand calls.
+ * Cite: as vmt_init_genrand; batching many generators: paper silent.
+ */
+int vmt_init_genrand_batch(vmt_ctx* ctx, int variant, const uint64_t* seeds, size_t count, uint32_t M,
+                           void* const* d_states, hipStream_t stream);
+
 /* Batched vmt_init_by_array: count states, state i keyed by
  * keys[i*key_len .. i*key_len + key_len - 1] (host array), all MT19937-32
  * with M lanes; d_states is a host array of count device pointers, each

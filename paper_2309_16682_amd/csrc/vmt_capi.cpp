@@ -750,6 +750,42 @@ int vmt_init_by_array(vmt_ctx* ctx, int variant, const uint32_t* key, size_t key
     return st;
 }
 
+int vmt_init_genrand_batch(vmt_ctx* ctx, int variant, const uint64_t* seeds, size_t count, uint32_t M,
+                           void* const* d_states, hipStream_t stream) {
+    if (!valid_variant(variant)) return fail(VMT_EINVAL, "unknown variant %d", variant);
+    if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);
+    if (count == 0) return set_device(ctx);
+    if (!seeds || !d_states) return fail(VMT_EINVAL, "null seeds or states");
+    if (count > (1u << 24)) return fail(VMT_EINVAL, "too many states");
+    for (size_t i = 0; i < count; i++)
+        if (!d_states[i] || (uintptr_t)d_states[i] % 256) return fail(VMT_EINVAL, "state %zu null or misaligned", i);
+    int st = vmt::reject_duplicate_states(d_states, count);  // two seedings of one window would race
+    if (st) return st;
+    st = set_device(ctx);
+    if (st) return st;
+    LaneTable* lt = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        st = lane_table(ctx, variant, M, &lt);
+        if (st) return st;
+    }
+    std::vector<vmt::InitTask> tasks(count);
+    for (size_t i = 0; i < count; i++)
+        tasks[i] = vmt::InitTask{static_cast<uint8_t*>(d_states[i]), nullptr, seeds[i], vmt::kSeedGenrand, 0};
+    const size_t task_bytes = count * sizeof(vmt::InitTask);
+    vmt::InitTask* d_tasks = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_tasks, task_bytes, stream);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(init batch): %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d_tasks, tasks.data(), task_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = vmt::launch_init(variant, M, d_tasks, tasks[0], (uint32_t)count, lt->d, lt->max_deg, stream);
+    (void)hipFreeAsync(d_tasks, stream);
+    if (e != hipSuccess) return hip_fail(e, "init batch");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (size_t i = 0; i < count; i++) ctx->reg[d_states[i]] = StateInfo{variant, M};
+    return VMT_OK;
+}
+
 int vmt_init_by_array_batch(vmt_ctx* ctx, const uint32_t* keys, size_t key_len, size_t count, uint32_t M,
                             void* const* d_states, hipStream_t stream) {
     if (!valid_M(M)) return fail(VMT_EINVAL, "M must be a power of two in [1, 64], got %u", M);

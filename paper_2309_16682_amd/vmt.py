@@ -62,6 +62,7 @@ def lib():
         "vmt_init_genrand": ([P, I, U64, U32, P, P], I),
         "vmt_init_by_array": ([P, I, P, SZ, U32, P, P], I),
         "vmt_init_by_array_batch": ([P, P, SZ, SZ, U32, P, P], I),
+        "vmt_init_genrand_batch": ([P, I, P, SZ, U32, P, P], I),
         "vmt_jump": ([P, P, P, SZ, P], I),
         "vmt_jump_pow2": ([P, P, U32, P], I),
         "vmt_jump_pow2_batch": ([P, P, P, SZ, P], I),
@@ -102,7 +103,7 @@ def lib():
 def exported_symbols() -> list:
     return [
         "vmt_last_error", "vmt_version", "vmt_ctx_create", "vmt_ctx_destroy", "vmt_state_bytes",
-        "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_jump", "vmt_jump_pow2",
+        "vmt_init_genrand", "vmt_init_by_array", "vmt_init_by_array_batch", "vmt_init_genrand_batch", "vmt_jump", "vmt_jump_pow2",
         "vmt_jump_pow2_batch", "vmt_generate_u32", "vmt_generate_u64", "vmt_uniform_f32", "vmt_uniform_f64",
         "vmt_batch_generate", "vmt_batch_generate_noalloc", "vmt_batch_plan_create", "vmt_batch_plan_launch", "vmt_batch_plan_destroy",
         "vmt_batch_plan_write_pattern", "vmt_calib_fill",
@@ -187,6 +188,17 @@ def vmt_init_by_array_batch(ctx, keys, M, d_states, stream=None):
         lib().vmt_init_by_array_batch(
             ctx, k.ctypes.data_as(ctypes.c_void_p), k.shape[1], k.shape[0], M, ptrs, _stream(stream)
         )
+    )
+
+
+def vmt_init_genrand_batch(ctx, variant, seeds, M, d_states, stream=None):
+    """seeds: one integer per state; d_states: list of state tensors (or raw device addresses)."""
+    sd = np.ascontiguousarray([int(x) for x in seeds], dtype=np.uint64)
+    assert sd.shape[0] == len(d_states)
+    ptrs = _ptr_array([s if isinstance(s, int) else s.data_ptr() for s in d_states])
+    return _check(
+        lib().vmt_init_genrand_batch(ctx, variant, sd.ctypes.data_as(ctypes.c_void_p), sd.shape[0], M, ptrs,
+                                     _stream(stream))
     )
 
 

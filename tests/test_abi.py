@@ -145,6 +145,9 @@ def test_calls_on_several_states_reject_a_state_given_twice():
         assert b"twice" in L.vmt_last_error()
         assert L.vmt_jump_pow2_batch(ctx, dup, ks, 3, None) == vmt.VMT_EINVAL
         assert b"twice" in L.vmt_last_error()
+        seeds = (ctypes.c_uint64 * 3)(1, 2, 3)
+        assert L.vmt_init_genrand_batch(ctx, 1, seeds, 3, 8, dup, None) == vmt.VMT_EINVAL
+        assert b"twice" in L.vmt_last_error()
         st = ctypes.c_int(0)
         assert not L.vmt_server_create(ctx, dup, 3, ctypes.c_void_p(4096), 4096, 4096, 0, 1, 0, 0, ctypes.byref(st))
         assert st.value == vmt.VMT_EINVAL and b"twice" in L.vmt_last_error()
@@ -152,6 +155,8 @@ def test_calls_on_several_states_reject_a_state_given_twice():
         ok = (ctypes.c_void_p * 3)(256, 512, 768)
         assert L.vmt_init_by_array_batch(ctx, keys, 4, 3, 16, ok, None) == vmt.VMT_EDEVICE
         assert L.vmt_jump_pow2_batch(ctx, ok, ks, 3, None) == vmt.VMT_EDEVICE
+        assert L.vmt_init_genrand_batch(ctx, 1, seeds, 3, 8, ok, None) == vmt.VMT_EDEVICE
+        assert L.vmt_init_genrand_batch(ctx, 8, seeds, 3, 8, ok, None) == vmt.VMT_EINVAL
         # vmt_batch_generate checks registration first; unknown states are a state error, never a race
         assert L.vmt_batch_generate(ctx, dup, lens, outs, 3, 0, None) in (vmt.VMT_EDEVICE, vmt.VMT_ESTATE)
     finally:

@@ -211,6 +211,27 @@ def test_init_by_array_batch_matches_single(ctx):
         np.testing.assert_array_equal(gen(ctx, states[i], MT32, 20000), ref)
 
 
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8), (SFMT, 4), (SFMT, 64), (vmt.VMT_SFMT607, 16)])
+def test_init_genrand_batch_matches_single(ctx, variant, M):
+    # one launch seeding many states equals seeding each alone (whole states, header included), and the
+    # streams are the oracle's
+    count = 37 if M < 64 else 9
+    seeds = [1, 5489, 2**32 - 1, 2**32, 2**63 + 12345] + list(range(700, 700 + count - 5))
+    say(f"case init_genrand_batch variant={variant} M={M} count={count}")
+    sb = vmt.vmt_state_bytes(variant, M)
+    pool = torch.zeros(count * sb, dtype=torch.uint8, device="cuda")
+    states = [pool[i * sb : (i + 1) * sb] for i in range(count)]
+    vmt.vmt_init_genrand_batch(ctx, variant, seeds, M, states)
+    for i in range(count):
+        one = torch.zeros(sb, dtype=torch.uint8, device="cuda")
+        vmt.vmt_init_genrand(ctx, variant, seeds[i], M, one)
+        torch.cuda.synchronize()
+        assert torch.equal(one, states[i]), f"state {i} (seed {seeds[i]})"
+    n = 2 * vmt.STATE_WORDS[variant] * (4 if variant in vmt.SFMT_FAMILY else 1) * M + 3
+    for i in (0, 4, count - 1):
+        np.testing.assert_array_equal(gen(ctx, states[i], variant, n), oracle_prefix(variant, M, seeds[i], n))
+
+
 @pytest.mark.parametrize("variant,M,kind", [(MT32, 16, vmt.VMT_OUT_U32), (MT32, 4, vmt.VMT_OUT_F32),
                                             (MT64, 8, vmt.VMT_OUT_U64), (MT64, 8, vmt.VMT_OUT_F64),
                                             (MT64, 2, vmt.VMT_OUT_F32), (SFMT, 4, vmt.VMT_OUT_U32),
