@@ -334,6 +334,37 @@ __device__ __forceinline__ T gload(const T* p) {
     return v;
 }
 
+// The same block with the lane's window in registers: R[k] holds sub-word j
+// of w_k on entry and of w_{k+N} on exit (the step that writes w_{k+N} is the
+// last to read w_k, and w_{k+MM} for k + MM >= N is the new word written
+// N - MM steps before, already in R). With every index a compile-time
+// constant the array stays in VGPRs across blocks, so a step issues no LDS
+// access: the recurrence, the two neighbour moves and the output store.
+template <int N, class Emit>
+__device__ __forceinline__ void sfmt_block_regs(uint32_t (&R)[N], int j, Emit emit) {
+    using P = SfmtP<N>;
+    constexpr int MM = P::MM;
+    const uint32_t K = j == 0 ? P::K0 : j == 1 ? P::K1 : j == 2 ? P::K2 : P::K3;
+    uint32_t c = R[N - 2], d = R[N - 1];
+    uint32_t cn = quad_next(c), dn = quad_next(d);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const uint32_t ak = R[k];
+        const uint32_t bk = R[k + MM < N ? k + MM : k + MM - N];
+        const uint32_t al = __builtin_amdgcn_alignbit(ak, quad_prev(ak), 32 - P::SL2);
+        const uint32_t cr = __builtin_amdgcn_alignbit(cn, c, P::SR2);
+        uint32_t r = xor3(ak, al, cr);
+        r = xor_and(r, bk >> P::SR1, K);
+        r ^= d << P::SL1;
+        R[k] = r;
+        emit(k, r);
+        c = d;
+        cn = dn;
+        d = r;
+        dn = quad_next(r);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // MT generation: one workgroup owns LPW lanes (lanes g*LPW ...) of a state.
 // ---------------------------------------------------------------------------
@@ -722,103 +753,93 @@ struct SfmtGen {
         return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
     }
 
-    static __device__ __forceinline__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos, uint4* win) {
+    // Lane group g (lanes g*LPW ...): quad q of the workgroup runs lane
+    // lane0 + q, its thread j sub-word j, with the lane's window in registers
+    // (sfmt_block_regs); threads past the group idle.
+    static __device__ __forceinline__ void run(uint8_t* state, OutT* out, uint64_t len, uint32_t g, bool write_pos) {
         state = uniform(state);
         out = uniform(out);
         len = uniform(len);
         StateHeader* hdr = reinterpret_cast<StateHeader*>(state);
         const uint32_t M = uniform(hdr->M);
         const uint32_t pos = uniform(hdr->pos);
-        uint4* gwin = reinterpret_cast<uint4*>(state + kHeaderBytes);
+        uint32_t* gw32 = reinterpret_cast<uint32_t*>(state + kHeaderBytes);  // sub-word j of word k, lane t: [(k M + t) 4 + j]
         const uint32_t B = 4u * N * M;  // uint32 elements per block
         if (len == 0) return;
         const int tid = threadIdx.x;
-        const int nthr = blockDim.x;
         const uint32_t lane0 = g * LPW;
         const uint64_t head = len < (uint64_t)(B - pos) ? len : (uint64_t)(B - pos);
         const uint64_t rest = len - head;
         const uint64_t nblocks = (rest + B - 1) / B;
-
-        for (int i = tid; i < N * LPW; i += nthr) {
-            const int k = i / LPW, t = i - (i / LPW) * LPW;
-            win[k * LPW + t] = gwin[(size_t)k * M + lane0 + t];
-        }
-        __syncthreads();
-        if (head) {
-            const uint32_t e0 = pos / 4, e1 = (uint32_t)((pos + head - 1) / 4);  // 128-bit elements touched
-            const uint32_t k0 = e0 / M, k1 = e1 / M;
-            for (uint32_t i = k0 * LPW + tid; i < (k1 + 1) * LPW; i += nthr) {
-                const uint32_t k = i / LPW, tl = i - (i / LPW) * LPW;
-                const uint32_t e = k * M + lane0 + tl;
-                const uint4 w = win[k * LPW + tl];
-#pragma unroll
-                for (uint32_t j = 0; j < 4; j++) {
-                    const uint32_t p = 4 * e + j;
-                    if (p >= pos && p < pos + head) {
-                        const uint32_t v = sub(w, j);
-                        if constexpr (OUT == 0) out[p - pos] = v;
-                        else out[p - pos] = to_f32(v);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // full blocks: lane group q of the workgroup, quad thread j owns sub-word j
         const QuadThread qt = sfmt_quad_thread(tid);
         const int q = qt.q, j = qt.j;
-        uint32_t* w32 = reinterpret_cast<uint32_t*>(win);
         if (q < LPW) {
-            for (uint64_t b = 0; b < nblocks; ++b) {
-                const uint64_t o0 = head + b * B;
-                const uint32_t lim = (len - o0) < (uint64_t)B ? (uint32_t)(len - o0) : B;
-                // output of word k's sub-word j: out[o0 + base + 4 M k], a running pointer. The
-                // stride is re-read in every block (readfirstlane is not hoisted out of the loop):
-                // otherwise the compiler keeps the N per-step offsets live across blocks.
-                const uint32_t step = __builtin_amdgcn_readfirstlane(4u * M);
-                uint32_t o = 4u * (lane0 + q) + j;
-                OutT* op = out + o0 + o;
-                if (lim == B) {  // a whole block: every output is in range, no per-step test
-                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
-                        gstore(op, map(r));
-                        op += step;
-                    });
-                } else {
-                    sfmt_block_quad<N>(w32 + 4 * q, w32 + 4 * q, 4 * LPW, j, [&](int, uint32_t r) {
-                        if (o < lim) gstore(op, map(r));
-                        o += step;
-                        op += step;
-                    });
+            const uint32_t o = 4u * (lane0 + q) + j;  // stream offset of this sub-word within a word row
+            const uint32_t step = __builtin_amdgcn_readfirstlane(4u * M);
+            uint32_t R[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) R[k] = gw32[k * step + o];
+            if (head) {  // the rest of the current block: words of the window at stream offsets [pos, pos + head)
+                uint32_t sth = step;  // opaque to the compiler, as below: the load addresses are not kept for this
+                asm volatile("" : "+s"(sth));
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const uint32_t p = k * sth + o;
+                    if (p >= pos && p < pos + (uint32_t)head) gstore(out + (p - pos), map(R[k]));
                 }
             }
-        }
-        __syncthreads();
-        if (nblocks) {
-            for (int i = tid; i < N * LPW; i += nthr) {
-                const int k = i / LPW, t = i - (i / LPW) * LPW;
-                gwin[(size_t)k * M + lane0 + t] = win[k * LPW + t];
+            // Whole blocks, then at most one partial block. The output of word k's sub-word j is
+            // out[o0 + step k + o]: a wave-uniform base (scalar registers, advanced by the scalar unit)
+            // plus this thread's fixed offset, so a step spends no vector instruction on addressing.
+            const uint64_t nfull = rest / B;
+            for (uint64_t b = 0; b < nfull; ++b) {
+                uint64_t base = reinterpret_cast<uint64_t>(out + (head + b * B));
+                sfmt_block_regs<N>(R, j, [&](int, uint32_t r) {
+                    gstore(reinterpret_cast<OutT*>(uniform(base)) + o, map(r));
+                    base += (uint64_t)step * sizeof(OutT);
+                });
+            }
+            if (nfull < nblocks) {
+                const uint64_t o0 = head + nfull * B;
+                const uint32_t lim = (uint32_t)(len - o0);
+                const int kmax = o < lim ? (int)((lim - o + step - 1) / step) : 0;  // steps whose output is in range
+                uint64_t base = reinterpret_cast<uint64_t>(out + o0);
+                sfmt_block_regs<N>(R, j, [&](int k, uint32_t r) {
+                    if (k < kmax) gstore(reinterpret_cast<OutT*>(uniform(base)) + o, map(r));
+                    base += (uint64_t)step * sizeof(OutT);
+                });
+            }
+            if (nblocks) {
+                // a stride the compiler cannot match with the loads' above: it recomputes these
+                // addresses instead of keeping N of them live through the block loop (likewise the head's)
+                uint32_t st2 = step;
+                asm volatile("" : "+s"(st2));
+#pragma unroll
+                for (int k = 0; k < N; ++k) gw32[k * st2 + o] = R[k];
             }
         }
-        if (write_pos && tid == 0)
-            hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
+        if (write_pos) {
+            __syncthreads();  // every quad has read the header before it changes
+            if (tid == 0)
+                hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
+        }
     }
 };
 
 template <int N, int LPW, int OUT>
-__global__ __launch_bounds__(64) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len, int write_pos) {
+__global__ __launch_bounds__(64, 3) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len, int write_pos) {
     using G = SfmtGen<N, LPW, OUT>;
-    __shared__ uint4 win[N * LPW];
-    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
+    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0);
 }
 
 // Batched SFMT generation: workgroup (g, t) runs lane group g of task t.
 // With several groups per state the positions are fixed afterwards
 // (finalize_batch_pos), since every group reads the header first.
 template <int N, int LPW, int OUT>
-__global__ __launch_bounds__(64) void batch_sfmt_kernel(const BatchTask* tasks) {
+__global__ __launch_bounds__(64, 3) void batch_sfmt_kernel(const BatchTask* tasks) {
     using G = SfmtGen<N, LPW, OUT>;
-    __shared__ uint4 win[N * LPW];
     const BatchTask task = tasks[blockIdx.y];
-    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
+    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1);
 }
 
 // Batched MT generation by lane groups (the chunks of a split call):
