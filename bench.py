@@ -98,6 +98,7 @@ def parse():
     ap.add_argument("--only-batch", action="store_true", help="time the batched step only (for profiling)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving section only")
     ap.add_argument("--only-check", action="store_true", help="run the linear-complexity self-check section only")
+    ap.add_argument("--only-jumps", action="store_true", help="run the jump section only")
     ap.add_argument("--only-variants", type=str, default=None,
                     help="run these batched family lines only (comma-separated names, e.g. mt64_M8_u64, or 'all')")
     ap.add_argument("--only-single", type=str, default=None,
@@ -190,10 +191,11 @@ def cpu_baseline(seconds: float, threads: int) -> dict:
 
 def calibrate(torch, ctx=None, gib: int = 4, reps: int = 3) -> dict:
     """A plain device copy (read n + write n bytes), fill (torch's 16-byte
-    vector stores), hipMemsetAsync and the library's own 16-byte fill, plain
-    and nontemporal (write n bytes) of `gib` GiB: the copy's FETCH_SIZE /
-    WRITE_SIZE readings give the counters' scale, the fill and memset rates
-    the write ceiling measured on this device."""
+    vector stores), hipMemsetAsync and the library's own 16-byte fills
+    (4 KiB pieces in address order; two contiguous regions per CU, plain and
+    nontemporal) of `gib` GiB: the copy's FETCH_SIZE / WRITE_SIZE readings
+    give the counters' scale, the fill and memset rates the write ceilings
+    measured on this device."""
     n = gib << 30
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -212,8 +214,9 @@ def calibrate(torch, ctx=None, gib: int = 4, reps: int = 3) -> dict:
     if ctx is not None:
         from paper_2309_16682_amd import vmt
 
-        legs += [("fill_lib", lambda: vmt.vmt_calib_fill(ctx, dst), n),
-                 ("fill_lib_nt", lambda: vmt.vmt_calib_fill(ctx, dst, nontemporal=True), n)]
+        legs += [("fill_pieces", lambda: vmt.vmt_calib_fill(ctx, dst), n),
+                 ("fill_regions", lambda: vmt.vmt_calib_fill(ctx, dst, regions=True), n),
+                 ("fill_regions_nt", lambda: vmt.vmt_calib_fill(ctx, dst, regions=True, nontemporal=True), n)]
     for name, fn, moved in legs:
         fn()
         torch.cuda.synchronize()
@@ -379,6 +382,61 @@ def batched_variants(ctx, torch, args, only=None) -> dict:
         log(f"batched {name}: {res[name]}")
         del arena, pool, states
         torch.cuda.empty_cache()
+    return res
+
+
+# Jumps by 2^100 steps per lane: one state, and batches of states (the sliced grouped form up to 1,024 lane jumps,
+# the per-coefficient form beyond). name, variant, lanes, states
+JUMP_CASES = (
+    ("mt32_M16_1state", 0, 16, 1),
+    ("mt64_M8_1state", 1, 8, 1),
+    ("sfmt_M4_1state", 2, 4, 1),
+    ("mt64_M8_128states", 1, 8, 128),
+    ("mt32_M16_256states", 0, 16, 256),
+)
+
+
+def jumps(ctx, torch, reps: int = 10, k: int = 100) -> dict:
+    """Time vmt_jump_pow2 / vmt_jump_pow2_batch by 2^k. Algorithmic LDS reads
+    per lane jump: one window (2,496 bytes for every variant) per nonzero
+    group of 4 coefficients of g = t^(2^k) mod mu (grouped form, up to 1,024
+    lane jumps per call) or per set coefficient (beyond); against the LDS
+    peak of 256 CUs x 128 B/clock x 2.4 GHz."""
+    from paper_2309_16682_amd import vmt
+
+    res = {}
+    for name, variant, M, count in JUMP_CASES:
+        g = vmt.vmt_jump_poly(ctx, variant, 1 << k)
+        nib = sum(1 for i in range(0, g.bit_length(), 4) if (g >> i) & 15)
+        bits = bin(g).count("1")
+        lanes = M * count
+        grouped = lanes <= 1024
+        win = (vmt.vmt_state_bytes(variant, M) - 256) // M  # bytes of one lane's window
+        lds = (nib if grouped else bits) * win
+        sb = vmt.vmt_state_bytes(variant, M)
+        pool = torch.empty(count * sb, dtype=torch.uint8, device="cuda")
+        states = [pool[i * sb : (i + 1) * sb] for i in range(count)]
+        vmt.vmt_init_genrand_batch(ctx, variant, [i + 1 for i in range(count)], M, states)
+        call = (lambda: vmt.vmt_jump_pow2(ctx, states[0], k)) if count == 1 else (
+            lambda: vmt.vmt_jump_pow2_batch(ctx, states, [k] * count))
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rate = lanes * lds / (ms * 1e-3)
+        res[name] = {"lane_jumps": lanes, "ms_per_call": round(ms, 4), "us_per_lane_jump": round(ms * 1e3 / lanes, 3),
+                     "form": "grouped, sliced over a workgroup per lane" if grouped else "per coefficient",
+                     "set_coefficients": bits, "nonzero_groups": nib, "lds_bytes_per_lane_jump": lds,
+                     "roofline": {"bound": "lds", "achieved": round(rate / 1e9, 1), "peak": LDS_PEAK_BYTES / 1e9,
+                                  "unit": "GB/s", "frac": round(rate / LDS_PEAK_BYTES, 4),
+                                  "scope": "whole call (jump kernel and position fix-up)"}}
+        log(f"jump {name}: {res[name]}")
+        del pool, states
     return res
 
 
@@ -591,6 +649,11 @@ def main():
         print(json.dumps({"batched_variants": batched_variants(ctx, torch, args, only)}), flush=True)
         vmt.vmt_ctx_destroy(ctx)
         return
+    if args.only_jumps:
+        ctx = vmt.vmt_ctx_create(0)
+        print(json.dumps({"jumps": jumps(ctx, torch)}), flush=True)
+        vmt.vmt_ctx_destroy(ctx)
+        return
     if args.only_check:
         ctx = vmt.vmt_ctx_create(0)
         print(json.dumps({"self_check": self_check(ctx, torch)}), flush=True)
@@ -771,8 +834,13 @@ def main():
             "measured_fill_GBps": ceiling["fill_GBps"],
             "measured_memset_GBps": ceiling["memset_GBps"],
             "frac_of_measured_fill": round(achieved / ceiling["fill_GBps"], 4),
-            "measured_fill_lib_GBps": ceiling.get("fill_lib_GBps"),
-            "measured_fill_lib_nt_GBps": ceiling.get("fill_lib_nt_GBps"),
+            # the library's own fills: 4 KiB pieces in address order, and two contiguous regions per CU
+            # written side by side (the pattern of many independent output streams)
+            "measured_fill_pieces_GBps": ceiling.get("fill_pieces_GBps"),
+            "measured_fill_regions_GBps": ceiling.get("fill_regions_GBps"),
+            "measured_fill_regions_nt_GBps": ceiling.get("fill_regions_nt_GBps"),
+            "frac_of_fill_regions": round(achieved / ceiling["fill_regions_GBps"], 4)
+            if ceiling.get("fill_regions_GBps") else None,
             "pattern_ceiling_GBps": round(np.mean(round_alg_bytes) / (pattern_ms * 1e-3) / 1e9, 1) if pattern_ms else None,
             "frac_of_pattern_ceiling": round(launch_ms_mean and pattern_ms / launch_ms_mean, 4) if pattern_ms else None,
             "alg_bytes_per_launch": int(np.mean(round_alg_bytes)),
@@ -822,6 +890,7 @@ def main():
         result["single_stream"] = single_streams(ctx, torch, args)
         result["call_size_sweep_mt32_M16"] = call_size_sweep(ctx, torch)
         result["self_check"] = self_check(ctx, torch)
+        result["jumps"] = jumps(ctx, torch)
 
     arena = out_base = None  # the batch arena is not needed any more
     torch.cuda.empty_cache()

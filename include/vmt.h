@@ -257,12 +257,16 @@ int vmt_batch_plan_destroy(vmt_batch_plan* plan);
  * V-MT19937-64 M=8 uint64 plans (VMT_EVARIANT otherwise). Must not overlap a
  * launch of the same plan (they share its queue counter).
  * vmt_calib_fill writes `bytes` (a multiple of 16, 16-byte aligned buffer)
- * with 16-byte stores, 4 KiB per workgroup and step, nontemporal if
- * `nontemporal` is nonzero: the plain write ceiling.
+ * with 16-byte stores. mode bit 0 = 0: one-shot workgroups each storing one
+ * 4 KiB piece, in address order (a plain fill, the sequential write
+ * ceiling); bit 0 = 1: two persistent workgroups per compute unit, each
+ * writing its own contiguous region in order (the pattern of many
+ * independent output streams, as batched generation writes). mode bit 1:
+ * nontemporal stores. VMT_EINVAL for a mode outside 0..3.
  * Cite: paper silent; a measurement aid.
  */
 int vmt_batch_plan_write_pattern(vmt_batch_plan* plan, hipStream_t stream);
-int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int nontemporal, hipStream_t stream);
+int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int mode, hipStream_t stream);
 
 /* Copy a state to or from host memory (bytes = vmt_state_bytes). Import
  * validates the header and registers the state with the context. Both

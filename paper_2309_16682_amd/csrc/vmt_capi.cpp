@@ -1018,11 +1018,12 @@ int vmt_batch_plan_write_pattern(vmt_batch_plan* plan, hipStream_t stream) {
     return VMT_OK;
 }
 
-int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int nontemporal, hipStream_t stream) {
+int vmt_calib_fill(vmt_ctx* ctx, void* d_buf, size_t bytes, int mode, hipStream_t stream) {
     int st = set_device(ctx);
     if (st) return st;
     if (!d_buf || bytes % 16 || (uintptr_t)d_buf % 16) return fail(VMT_EINVAL, "fill: buffer and size must be 16-byte aligned");
-    hipError_t e = vmt::launch_fill(d_buf, bytes, nontemporal != 0, vmt::device_cus(ctx->device), stream);
+    if (mode < 0 || mode > 3) return fail(VMT_EINVAL, "fill mode must be 0..3");
+    hipError_t e = vmt::launch_fill(d_buf, bytes, mode, vmt::device_cus(ctx->device), stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     return VMT_OK;
 }

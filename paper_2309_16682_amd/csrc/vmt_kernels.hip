@@ -723,16 +723,29 @@ __global__ __launch_bounds__((mt_threads<P, LANES, TV>()), (TV >= 2 ? 4 : 8)) vo
     }
 }
 
-// Measurement only: a plain write of n16 16-byte words of `v`, each
-// workgroup of 256 threads storing 4 KiB pieces, grid-stride.
+// Measurement only: writes of n16 16-byte words of `v` in two patterns.
+// fill_pieces: one-shot workgroups of 256 threads, each storing one 4 KiB
+// piece, in address order (a plain fill). fill_regions: `gridDim.x`
+// persistent workgroups, each writing its own contiguous region of `per16`
+// words in order (the last one the remainder), which is the output pattern
+// of many independent generators at once.
 template <bool NT>
-__global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint32_t v) {
+__device__ __forceinline__ void fill_store(uint4* p, uint32_t v) {
     using D = DwordVec<4>::type;
     const D d = {v, v, v, v};
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * 256) {
-        if constexpr (NT) __builtin_nontemporal_store(d, (VMT_GLOBAL D*)(p + i));
-        else *(VMT_GLOBAL D*)(p + i) = d;
-    }
+    if constexpr (NT) __builtin_nontemporal_store(d, (VMT_GLOBAL D*)p);
+    else *(VMT_GLOBAL D*)p = d;
+}
+template <bool NT>
+__global__ __launch_bounds__(256) void fill_pieces(uint4* p, uint64_t n16, uint32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) fill_store<NT>(p + i, v);
+}
+template <bool NT>
+__global__ __launch_bounds__(256) void fill_regions(uint4* p, uint64_t n16, uint64_t per16, uint32_t v) {
+    const uint64_t lo = (uint64_t)blockIdx.x * per16;
+    const uint64_t hi = blockIdx.x + 1 == gridDim.x ? n16 : lo + per16;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) fill_store<NT>(p + i, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1821,13 +1834,22 @@ hipError_t launch_write_pattern(uint32_t variant, uint32_t M, int out_kind, cons
     return hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, stream);
 }
 
-hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t cus, hipStream_t stream) {
+hipError_t launch_fill(void* d_buf, uint64_t bytes, int mode, uint32_t cus, hipStream_t stream) {
     const uint64_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
-    uint64_t grid = (n16 + 255) / 256;
-    if (grid > (uint64_t)cus * 16) grid = (uint64_t)cus * 16;
-    if (nontemporal) fill_kernel<true><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
-    else fill_kernel<false><<<(uint32_t)grid, 256, 0, stream>>>(static_cast<uint4*>(d_buf), n16, 0x5a5a5a5au);
+    uint4* p = static_cast<uint4*>(d_buf);
+    const bool nt = (mode & 2) != 0;
+    if ((mode & 1) == 0) {  // 4 KiB pieces, one per workgroup
+        const uint64_t grid = (n16 + 255) / 256;
+        if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+        if (nt) fill_pieces<true><<<(uint32_t)grid, 256, 0, stream>>>(p, n16, 0x5a5a5a5au);
+        else fill_pieces<false><<<(uint32_t)grid, 256, 0, stream>>>(p, n16, 0x5a5a5a5au);
+    } else {  // two regions per compute unit, like two resident generators per CU
+        const uint32_t grid = 2 * cus;
+        const uint64_t per16 = n16 / grid;
+        if (nt) fill_regions<true><<<grid, 256, 0, stream>>>(p, n16, per16, 0x5a5a5a5au);
+        else fill_regions<false><<<grid, 256, 0, stream>>>(p, n16, per16, 0x5a5a5a5au);
+    }
     return hipGetLastError();
 }
 

@@ -89,12 +89,13 @@ hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out
 // Measurement only. launch_write_pattern: the batch kernel's memory traffic
 // for the same tasks and shape without the twist (states unchanged;
 // V-MT19937-32 M = 16 and V-MT19937-64 M = 8 integer outputs).
-// launch_fill: a plain write of `bytes` (a multiple of 16) with 16-byte
-// stores, optionally nontemporal.
+// launch_fill: a write of `bytes` (a multiple of 16) with 16-byte stores;
+// mode bit 0: 4 KiB pieces in order (0) or two contiguous regions per CU
+// (1), bit 1: nontemporal stores.
 bool pattern_supported(uint32_t variant, uint32_t M, int out_kind);
 hipError_t launch_write_pattern(uint32_t variant, uint32_t M, int out_kind, const BatchShape& shape,
                                 const BatchTask* d_tasks, uint32_t count, uint32_t* d_counter, hipStream_t stream);
-hipError_t launch_fill(void* d_buf, uint64_t bytes, bool nontemporal, uint32_t cus, hipStream_t stream);
+hipError_t launch_fill(void* d_buf, uint64_t bytes, int mode, uint32_t cus, hipStream_t stream);
 
 // Allocation-free batch call. The task list and counters live in a
 // file-scope device array of kNoAllocMaxTasks tasks, one per device, shared

@@ -282,9 +282,10 @@ def vmt_batch_plan_write_pattern(plan, stream=None):
     return _check(lib().vmt_batch_plan_write_pattern(plan, _stream(stream)))
 
 
-def vmt_calib_fill(ctx, d_buf, nbytes=None, nontemporal=False, stream=None):
+def vmt_calib_fill(ctx, d_buf, nbytes=None, regions=False, nontemporal=False, stream=None):
     n = d_buf.numel() * d_buf.element_size() if nbytes is None else nbytes
-    return _check(lib().vmt_calib_fill(ctx, _dptr(d_buf), n, 1 if nontemporal else 0, _stream(stream)))
+    mode = (1 if regions else 0) | (2 if nontemporal else 0)
+    return _check(lib().vmt_calib_fill(ctx, _dptr(d_buf), n, mode, _stream(stream)))
 
 
 def vmt_state_export(ctx, d_state, stream=None) -> np.ndarray:
