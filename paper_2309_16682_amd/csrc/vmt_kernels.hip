@@ -635,12 +635,42 @@ struct MtGen {
     }
 };
 
+// Lane groups of one state write interleaved pieces of the same output lines
+// (LPW elements of every row of M). Workgroups are dispatched to the XCDs
+// round robin by linear id, and each XCD has its own L2: the groups of a
+// state are therefore placed on one XCD (linear ids that agree mod kXcds), so
+// that its L2 merges the pieces of a line before they go to memory. A launch
+// covers `states` x `groups` work items on a grid of kXcds * groups *
+// ceil(states / kXcds) workgroups; ids that map past the last state exit.
+// State t goes to XCD (t + xoff) mod kXcds: single-state launches pass an
+// offset taken from the state's address, so that concurrent launches for
+// different states spread over the XCDs.
+#ifndef VMT_XCD_MAP
+#define VMT_XCD_MAP 1
+#endif
+constexpr uint32_t kXcds = 8;  // MI355X: 8 XCDs of 32 CUs
+struct GroupSlot {
+    uint32_t state, group;
+};
+__device__ __forceinline__ GroupSlot group_slot(uint32_t linear, uint32_t groups, uint32_t xoff) {
+    if (!VMT_XCD_MAP) return GroupSlot{linear / groups, linear - (linear / groups) * groups};
+    const uint32_t x = linear % kXcds, s = linear / kXcds;  // slot s on XCD x
+    const uint32_t t = (x + kXcds - xoff) % kXcds;          // states t, t + kXcds, ... run on XCD x
+    return GroupSlot{(s / groups) * kXcds + t, s - (s / groups) * groups};
+}
+inline uint32_t group_grid(uint32_t states, uint32_t groups) {
+    return VMT_XCD_MAP ? kXcds * groups * ((states + kXcds - 1) / kXcds) : states * groups;
+}
+inline uint32_t state_xcd(const void* state) { return (uint32_t)(((uintptr_t)state >> 8) % kXcds); }
+
 template <class P, int LPW, int OUT>
 __global__ __launch_bounds__((mt_threads<P, LPW>())) void gen_mt_kernel(uint8_t* state, void* out, uint64_t len,
-                                                                     int write_pos) {
+                                                                     int write_pos, uint32_t groups, uint32_t xoff) {
     using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
     __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LPW];
-    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0, win);
+    const GroupSlot gs = group_slot(blockIdx.x, groups, xoff);
+    if (gs.state != 0) return;
+    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, gs.group, write_pos != 0, win);
 }
 
 // Persistent batched generation: each workgroup pops states from a counter;
@@ -860,11 +890,14 @@ __global__ __launch_bounds__(64, 3) void batch_sfmt_kernel(const BatchTask* task
 // a chunk's M lanes spread over M / LPW workgroups. With several groups per
 // state the positions are fixed afterwards (finalize_batch_pos).
 template <class P, int LPW, int OUT>
-__global__ __launch_bounds__((mt_threads<P, LPW>())) void batch_gen_mt_kernel(const BatchTask* tasks) {
+__global__ __launch_bounds__((mt_threads<P, LPW>())) void batch_gen_mt_kernel(const BatchTask* tasks, uint32_t count,
+                                                                           uint32_t groups) {
     using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
     __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LPW];
-    const BatchTask task = tasks[blockIdx.y];
-    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1, win);
+    const GroupSlot gs = group_slot(blockIdx.x, groups, 0);
+    if (gs.state >= count) return;
+    const BatchTask task = tasks[gs.state];
+    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, gs.group, groups == 1, win);
 }
 
 // Copy whole states (header and window; `bytes` a multiple of 16): task y
@@ -1632,21 +1665,23 @@ bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind
 
 hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, uint8_t* d_state, void* d_out,
                            uint64_t len, hipStream_t stream) {
-    const dim3 grid(M / lpw);
+    const uint32_t groups = M / lpw;
+    const dim3 grid(is_sfmt(variant) ? groups : group_grid(1, groups));
+    const uint32_t xoff = state_xcd(d_state);
     const int wp = (lpw == M) ? 1 : 0;
     if (variant == kMT32) {
         if (out_kind == kOutU32) {
-            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         } else {
-            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         }
     } else if (variant == kMT64) {
         if (out_kind == kOutU64) {
-            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         } else if (out_kind == kOutF64) {
-            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         } else {
-            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp))
+            VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         }
     } else {
         const dim3 block(64);
@@ -1753,20 +1788,21 @@ hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out
 hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
                                uint32_t count, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    const dim3 grid(M / lpw, count);
+    const uint32_t groups = M / lpw;
+    const dim3 grid(group_grid(count, groups));
     if (variant == kMT32) {
         if (out_kind == kOutU32) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups))
         } else {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups))
         }
     } else {
         if (out_kind == kOutU64) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
         } else if (out_kind == kOutF64) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
         } else {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
         }
     }
     hipError_t e = hipGetLastError();
