@@ -589,7 +589,8 @@ def serving_capacity(ctx, seconds: float = 2.0, warm: float = 0.5) -> dict:
     rate and the p99 wait for admission stays under 50 ms. The capacity is the
     highest sustained rate, with its delivered GB/s as a fraction of 8 TB/s."""
     out = {}
-    for label, mode, chunk, rates in (("batched_split", 4, 1 << 20, (20e3, 40e3, 80e3, 160e3, 320e3)),
+    for label, mode, chunk, rates in (("batched_split", 4, 1 << 20, (20e3, 40e3, 60e3, 80e3, 160e3)),
+                                      ("batched", 0, 1 << 20, (20e3, 40e3, 60e3, 80e3, 160e3)),
                                       ("plain", 1, 0, (500.0, 1e3, 2e3, 4e3))):
         rows = []
         for rate in rates:
