@@ -589,7 +589,10 @@ def serving_capacity(ctx, seconds: float = 2.0, warm: float = 0.5) -> dict:
     rate and the p99 wait for admission stays under 50 ms. The capacity is the
     highest sustained rate, with its delivered GB/s as a fraction of 8 TB/s."""
     out = {}
+    # splitting with chunks of 2^20 (the 20k rows above) and 2^21 elements: larger chunks need fewer jumps per
+    # request (more capacity) and leave the largest requests on fewer workgroups (longer p99 at low load)
     for label, mode, chunk, rates in (("batched_split", 4, 1 << 20, (20e3, 40e3, 60e3, 80e3, 160e3)),
+                                      ("batched_split_chunk2^21", 4, 1 << 21, (20e3, 40e3, 60e3, 80e3, 100e3, 160e3)),
                                       ("batched", 0, 1 << 20, (20e3, 40e3, 60e3, 80e3, 160e3)),
                                       ("plain", 1, 0, (500.0, 1e3, 2e3, 4e3))):
         rows = []

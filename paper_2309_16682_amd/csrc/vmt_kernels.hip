@@ -809,7 +809,7 @@ struct SfmtGen {
         uint32_t* gw32 = reinterpret_cast<uint32_t*>(state + kHeaderBytes);  // sub-word j of word k, lane t: [(k M + t) 4 + j]
         const uint32_t B = 4u * N * M;  // uint32 elements per block
         if (len == 0) return;
-        const int tid = threadIdx.x;
+        const int tid = threadIdx.x & 63;  // one wavefront runs the lane group
         const uint32_t lane0 = g * LPW;
         const uint64_t head = len < (uint64_t)(B - pos) ? len : (uint64_t)(B - pos);
         const uint64_t rest = len - head;
@@ -861,28 +861,40 @@ struct SfmtGen {
                 for (int k = 0; k < N; ++k) gw32[k * st2 + o] = R[k];
             }
         }
-        if (write_pos) {
-            __syncthreads();  // every quad has read the header before it changes
-            if (tid == 0)
-                hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
-        }
+        // the wavefront read the header above, in program order, before its lane 0 writes it here
+        if (write_pos && tid == 0)
+            hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * (uint64_t)B) : (uint32_t)(pos + head);
     }
 };
 
+// Four wavefronts per workgroup, each running one lane group (of one task)
+// on its own: the four land on the four SIMDs of a compute unit. One chain
+// per SIMD matters, since a chain is issue-bound: two wavefronts on one SIMD
+// halve each one's step rate, and separate one-wavefront workgroups were
+// found to pair up on SIMDs.
+constexpr int kSfmtWavesPerWg = 4;
+
 template <int N, int LPW, int OUT>
-__global__ __launch_bounds__(64, 3) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len, int write_pos) {
+__global__ __launch_bounds__(64 * kSfmtWavesPerWg, 3) void gen_sfmt_kernel(uint8_t* state, void* out, uint64_t len,
+                                                                         int write_pos, uint32_t groups) {
     using G = SfmtGen<N, LPW, OUT>;
-    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, blockIdx.x, write_pos != 0);
+    const uint32_t g = blockIdx.x * kSfmtWavesPerWg + uniform((uint32_t)threadIdx.x >> 6);
+    if (g >= groups) return;
+    G::run(state, reinterpret_cast<typename G::OutT*>(out), len, g, write_pos != 0);
 }
 
 // Batched SFMT generation: workgroup (g, t) runs lane group g of task t.
 // With several groups per state the positions are fixed afterwards
 // (finalize_batch_pos), since every group reads the header first.
 template <int N, int LPW, int OUT>
-__global__ __launch_bounds__(64, 3) void batch_sfmt_kernel(const BatchTask* tasks) {
+__global__ __launch_bounds__(64 * kSfmtWavesPerWg, 3) void batch_sfmt_kernel(const BatchTask* tasks, uint32_t count,
+                                                                           uint32_t groups) {
     using G = SfmtGen<N, LPW, OUT>;
-    const BatchTask task = tasks[blockIdx.y];
-    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, blockIdx.x, gridDim.x == 1);
+    const uint32_t item = blockIdx.x * kSfmtWavesPerWg + uniform((uint32_t)threadIdx.x >> 6);
+    const uint32_t t = item / groups, g = item - t * groups;
+    if (t >= count) return;
+    const BatchTask task = tasks[t];
+    G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, g, groups == 1);
 }
 
 // Batched MT generation by lane groups (the chunks of a split call):
@@ -1684,11 +1696,11 @@ hipError_t launch_generate(uint32_t variant, uint32_t M, uint32_t lpw, int out_k
             VMT_LPW_SWITCH(lpw, gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_state, d_out, len, wp, groups, xoff))
         }
     } else {
-        const dim3 block(64);
+        const dim3 sgrid((groups + kSfmtWavesPerWg - 1) / kSfmtWavesPerWg), block(64 * kSfmtWavesPerWg);
         if (out_kind == kOutU32) {
-            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_state, d_out, len, wp)))
+            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 0><<<sgrid, block, 0, stream>>>(d_state, d_out, len, wp, groups)))
         } else {
-            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_state, d_out, len, wp)))
+            VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, gen_sfmt_kernel<NN, LL, 1><<<sgrid, block, 0, stream>>>(d_state, d_out, len, wp, groups)))
         }
     }
     hipError_t e = hipGetLastError();
@@ -1773,11 +1785,13 @@ uint32_t device_cus(int device) {
 hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
                              uint32_t count, hipStream_t stream) {
     if (count == 0) return hipSuccess;
-    const dim3 grid(M / lpw, count), block(64);
+    const uint32_t groups = M / lpw;
+    const uint64_t items = (uint64_t)count * groups;
+    const dim3 grid((uint32_t)((items + kSfmtWavesPerWg - 1) / kSfmtWavesPerWg)), block(64 * kSfmtWavesPerWg);
     if (out_kind == kOutU32) {
-        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_tasks)))
+        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 0><<<grid, block, 0, stream>>>(d_tasks, count, groups)))
     } else {
-        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_tasks)))
+        VMT_SFMT_SWITCH(variant, VMT_LPW_SWITCH(lpw, batch_sfmt_kernel<NN, LL, 1><<<grid, block, 0, stream>>>(d_tasks, count, groups)))
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || lpw == M) return e;
