@@ -1502,6 +1502,110 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
     }
 }
 
+// Derived rows of window b from two raw blocks held elsewhere (x[m] is
+// lo[m] for m < N, hi[m - N] above): row 0 receives the raw words of the
+// window, rows 1 .. 7 the patterns as in derive_rows.
+template <class W, int N>
+__device__ __forceinline__ void derive_rows_from(W* rows, int rstride, const W* lo, const W* hi, int tid, int nthr) {
+    for (int m = tid; m < 2 * N; m += nthr) {
+        const W z = zero_w<W>();
+        auto x = [&](int i) { return i < N ? lo[i] : (i < 2 * N ? hi[i - N] : z); };
+        const W x0 = x(m), x1 = x(m + 1), x2 = x(m + 2), x3 = x(m + 3);
+        const W d3 = xorw(x0, x1), d5 = xorw(x0, x2), d7 = xorw(d3, x2);
+        rows[m] = x0;
+        rows[1 * rstride + m] = d3;
+        rows[2 * rstride + m] = d5;
+        rows[3 * rstride + m] = d7;
+        rows[4 * rstride + m] = xorw(x0, x3);
+        rows[5 * rstride + m] = xorw(d3, x3);
+        rows[6 * rstride + m] = xorw(d5, x3);
+        rows[7 * rstride + m] = xorw(d7, x3);
+    }
+}
+
+// One raw block of one lane by the chain (the four threads of a quad), as a
+// call: its registers are then not allocated alongside the summing code's,
+// which keeps the split jump's workgroups small enough for two per CU.
+template <int N>
+__device__ __attribute__((noinline)) void sfmt_chain_block(const uint32_t* src, uint32_t* dst, int j) {
+    sfmt_block_quad<N>(src, dst, 4, j, [](int, uint32_t) {});
+}
+
+// split_jump_kernel for SFMT, whose raw rows come from the serial 128-bit
+// chain: the workgroup has one more wavefront, which runs the lane's chain
+// one block ahead into a ring of three raw blocks in LDS while the CPW other
+// wavefronts sum their copies' polynomials over the current window's derived
+// rows. Window b is raw blocks b and b + 1; the chain writes block b + 2 into
+// the ring slot that held block b - 1, which no one reads any more (window b's
+// rows were derived before its sums began). Per block: sums and chain side
+// by side, a barrier, the rows of window b + 1 derived by every wavefront, a
+// barrier.
+template <int N, int CPW>
+__global__ __launch_bounds__((CPW + 1) * 64) void split_jump_sfmt_kernel(const uint8_t* src, const JumpTask* tasks,
+                                                                         uint32_t count, uint32_t M) {
+    using W = uint4;
+    constexpr int S = (N + 63) / 64;
+    constexpr int RW = jump_row_words<N, true>();
+    __shared__ __attribute__((aligned(16))) W rows[RW + jump_pad_words<N>()];
+    __shared__ __attribute__((aligned(16))) W ring[3 * N];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool chain_wave = w == CPW;
+    const uint32_t t = blockIdx.x % M;  // lane of the state
+    const uint32_t first = (blockIdx.x / M) * CPW;
+    const uint32_t mine = first + w;
+    const bool active = !chain_wave && mine < count;
+    const StateHeader* h = reinterpret_cast<const StateHeader*>(src);
+    const int k = (int)uniform((uint32_t)(h->pos / (4u * M)));  // words of every lane already consumed
+    int max_deg = 0;  // the workgroup's blocks run to the highest degree among its copies' polynomials
+    for (uint32_t i = first; i < first + CPW && i < count; ++i) max_deg = max(max_deg, (int)tasks[i].max_deg);
+    max_deg = (int)uniform((uint32_t)max_deg);
+    uint8_t* dst = nullptr;
+    const uint64_t* poly = nullptr;
+    int my_deg = -1;
+    if (active) {
+        dst = uniform(tasks[mine].state);
+        poly = uniform(tasks[mine].poly);
+        my_deg = (int)uniform(tasks[mine].max_deg);
+    }
+    // the chain: quad 0 of the chain wavefront, thread j holding sub-word j
+    const QuadThread qt = sfmt_quad_thread(lane);
+    const bool chainer = chain_wave && qt.q == 0;
+    auto chain_block = [&](int from, int to) {  // raw block `to` (a ring slot) from block `from`
+        if (chainer)
+            sfmt_chain_block<N>(reinterpret_cast<const uint32_t*>(ring + from * N), reinterpret_cast<uint32_t*>(ring + to * N),
+                                qt.j);
+    };
+    const W* gsrc = reinterpret_cast<const W*>(src + kHeaderBytes);
+    for (int j = tid; j < N; j += nthr) ring[j] = gsrc[(size_t)j * M + t];
+    __syncthreads();
+    chain_block(0, 1);
+    __syncthreads();
+    derive_rows_from<W, N>(rows, 2 * N, ring, ring + N, tid, nthr);
+    __syncthreads();
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    const int last_b = (k + max_deg) / N;
+    for (int b = 0; b <= last_b; ++b) {
+        if (active) accumulate_block4<W, N, true>(acc, rows, 2 * N, poly, k, b, my_deg, lane, 0, 1);
+        if (b < last_b) chain_block((b + 1) % 3, (b + 2) % 3);  // window b + 1 needs block b + 2
+        __syncthreads();
+        if (b == last_b) break;
+        derive_rows_from<W, N>(rows, 2 * N, ring + ((b + 1) % 3) * N, ring + ((b + 2) % 3) * N, tid, nthr);
+        __syncthreads();
+    }
+    if (active) {
+        W* gdst = reinterpret_cast<W*>(dst + kHeaderBytes);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = lane + 64 * s;
+            if (j < N) gdst[(size_t)j * M + t] = acc[s];
+        }
+    }
+}
+
 __global__ void finalize_jump_pos(const JumpTask* tasks, JumpTask one, uint32_t count) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -1651,7 +1755,13 @@ hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src,
     } else if (variant == kMT64) {
         VMT_CPW_SWITCH(cpw, split_jump_kernel<uint64_t, 312, CC><<<grid, block, 0, stream>>>(d_src, d_tasks, count, M))
     } else {
-        VMT_SFMT_SWITCH(variant, VMT_CPW_SWITCH(cpw, split_jump_kernel<uint4, NN, CC><<<grid, block, 0, stream>>>(d_src, d_tasks, count, M)))
+        // at most 8 copies per workgroup here: one more wavefront runs the chain, within 1,024 threads
+        const int scpw = cpw > 8 ? 8 : cpw;
+        const dim3 sgrid(M * ((count + scpw - 1) / scpw)), sblock((scpw + 1) * 64);
+        if (scpw == 4)
+            VMT_SFMT_SWITCH(variant, (split_jump_sfmt_kernel<NN, 4><<<sgrid, sblock, 0, stream>>>(d_src, d_tasks, count, M)))
+        else
+            VMT_SFMT_SWITCH(variant, (split_jump_sfmt_kernel<NN, 8><<<sgrid, sblock, 0, stream>>>(d_src, d_tasks, count, M)))
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
