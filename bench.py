@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "5a70c1e2a717e4f9e7247ab91b8a635657be1c592f85c1f1adc3a78c89932e71",
+    "kernel_fingerprint": "aac664d8f3bdd5a108108b8302347cb2edc3fdcc55f55e8fab1baaf49941907c",
     "shapes": {
-        (512, 16, 2): (878044331, 96283548107),
-        (512, 8, 2): (878088448, 96283547851),
-        (256, 16, 2): (878164693, 96283547797),
-        (256, 8, 3): (878276779, 96283564341),
-        (960, 16, 2): (878073088, 96283549333),
+        (512, 16, 2): (878101717, 96283548245),
+        (512, 8, 2): (878114475, 96283547872),
+        (256, 16, 2): (878140373, 96283547904),
+        (256, 8, 3): (878355456, 96283564235),
+        (960, 16, 2): (878076971, 96283549803),
     },
 }
 
