@@ -425,11 +425,13 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t off_bt = (C - 1) * sbs;
     const size_t off_jt = off_bt + (C * sizeof(vmt::BatchTask) + 255) / 256 * 256;
     const size_t off_ctr = off_jt + ((C - 1) * sizeof(vmt::JumpTask) + 255) / 256 * 256;
-    const size_t total = off_ctr + 256;
+    const size_t off_parts = off_ctr + 256;
+    const size_t parts_bytes = vmt::jump_parts_bytes(info.variant, M, C - 1);
+    const size_t total = off_parts + parts_bytes;
     uint8_t* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, total, stream);
     if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
-    std::vector<uint8_t> host(total - off_bt, 0);
+    std::vector<uint8_t> host(off_parts - off_bt, 0);
     auto* bt = reinterpret_cast<vmt::BatchTask*>(host.data());
     auto* jt = reinterpret_cast<vmt::JumpTask*>(host.data() + (off_jt - off_bt));
     for (uint64_t c = 0; c < C; c++) {
@@ -443,7 +445,9 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     e = hipMemcpyAsync(buf + off_bt, host.data(), off_ctr - off_bt, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = vmt::launch_replicate(d_state, buf, (uint32_t)sb, sbs, (uint32_t)(C - 1), stream);
     // copy 0 is chunk 0: it is not jumped and holds the window every other chunk starts from
-    if (e == hipSuccess) e = vmt::launch_split_jump(info.variant, M, buf, d_jt, jt[0], (uint32_t)(C - 1), stream);
+    if (e == hipSuccess)
+        e = vmt::launch_split_jump(info.variant, M, buf, d_jt, jt[0], (uint32_t)(C - 1), stream,
+                                   parts_bytes ? buf + off_parts : nullptr);
     if (e == hipSuccess) {
         if (vmt::is_sfmt(info.variant)) {
             e = vmt::launch_batch_sfmt(info.variant, M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
@@ -507,6 +511,21 @@ int init_common(vmt_ctx* ctx, int variant, uint32_t M, void* d_state, const vmt:
     return VMT_OK;
 }
 
+// A jump launch with, where it applies, the scratch for lane sums split over
+// several workgroups (stream-ordered, freed behind the launches).
+hipError_t jump_launch(uint32_t variant, uint32_t M, const vmt::JumpTask* d_tasks, const vmt::JumpTask& one,
+                       uint32_t count, hipStream_t stream) {
+    const size_t pb = vmt::jump_parts_bytes(variant, M, count);
+    void* d_parts = nullptr;
+    if (pb) {
+        hipError_t e = hipMallocAsync(&d_parts, pb, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = vmt::launch_jump(variant, M, d_tasks, one, count, stream, d_parts);
+    if (d_parts) (void)hipFreeAsync(d_parts, stream);
+    return e;
+}
+
 int jump_with(vmt_ctx* ctx, void* d_state, const std::vector<uint64_t>& dist, const Words* known, hipStream_t stream) {
     int st = set_device(ctx);
     if (st) return st;
@@ -520,7 +539,7 @@ int jump_with(vmt_ctx* ctx, void* d_state, const std::vector<uint64_t>& dist, co
         if (st) return st;
     }
     vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
-    hipError_t e = vmt::launch_jump(info.variant, info.M, nullptr, task, 1, stream);
+    hipError_t e = jump_launch(info.variant, info.M, nullptr, task, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "jump launch");
     return VMT_OK;
 }
@@ -853,7 +872,7 @@ int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream) {
         if (st) return st;
     }
     vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
-    hipError_t e = vmt::launch_jump(info.variant, info.M, nullptr, task, 1, stream);
+    hipError_t e = jump_launch(info.variant, info.M, nullptr, task, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "jump launch");
     return VMT_OK;
 }
@@ -883,7 +902,7 @@ int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks,
     hipError_t e = hipMallocAsync((void**)&d_tasks, count * sizeof(vmt::JumpTask), stream);
     if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(jump tasks): %s", hipGetErrorString(e));
     e = hipMemcpyAsync(d_tasks, tasks.data(), count * sizeof(vmt::JumpTask), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = vmt::launch_jump(info.variant, info.M, d_tasks, tasks[0], (uint32_t)count, stream);
+    if (e == hipSuccess) e = jump_launch(info.variant, info.M, d_tasks, tasks[0], (uint32_t)count, stream);
     (void)hipFreeAsync(d_tasks, stream);
     if (e != hipSuccess) return hip_fail(e, "jump batch");
     return VMT_OK;

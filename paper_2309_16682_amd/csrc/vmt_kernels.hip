@@ -1437,6 +1437,141 @@ __global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* task
     }
 }
 
+#ifndef VMT_PART_RATIO_MT32
+#define VMT_PART_RATIO_MT32 0.06f
+#endif
+#ifndef VMT_PART_RATIO_MT64
+#define VMT_PART_RATIO_MT64 0.1f
+#endif
+
+// First block of part p of `parts` over the nb blocks of a lane jump. A part
+// that starts at block b first twists its raw row b times without summing, so
+// later parts get fewer blocks: with r the cost of a bare twist relative to a
+// summed block, part p's share is q^p (q = 1 - r) of the first part's, and
+// each part's twists plus sums come to about the same time. Every workgroup
+// of a lane jump evaluates this in the same order, so the parts tile the
+// blocks exactly.
+__device__ __forceinline__ int part_start(int p, int parts, int nb, float r) {
+    const float q = 1.0f - r;
+    float c = 0.0f, total = 0.0f, w = 1.0f;
+    for (int i = 0; i < parts; ++i) {
+        if (i == p) c = total;
+        total += w;
+        w *= q;
+    }
+    if (p >= parts) return nb;
+    const int b = (int)(nb * (c / total) + 0.5f);
+    return b < nb ? b : nb;
+}
+
+// One part of an MT lane jump (jumps of few lanes). The sum over g's
+// coefficients is linear, so it splits over ranges of blocks: workgroup
+// (task, lane t, part p) sums blocks [b0, b1) of lane t's raw sequence, its
+// WPL wavefronts slicing each block's groups as in the sliced jump, and
+// writes the partial window (N contiguous words) to `partial`. Before its
+// first block it twists the lane's row from the window b0 times (two N-word
+// halves of LDS in turn, one barrier per block). A separate launch XORs the
+// parts into the state (reduce_jump_parts). All parts read the window and the
+// position before any of them is replaced.
+template <class P, int WPL>
+__global__ __launch_bounds__(WPL * 64) void jump_part_kernel(const JumpTask* tasks, JumpTask one, uint32_t M,
+                                                             uint32_t parts, typename P::W* partial, float ratio) {
+    using W = typename P::W;
+    constexpr int N = P::N;
+    constexpr int S = (N + 63) / 64;
+    constexpr int RW = jump_row_words<N, true>();
+    static_assert(WPL * N <= RW, "the wavefronts' partial sums are staged in the row buffer");
+    __shared__ __attribute__((aligned(16))) W buf[RW + jump_pad_words<N>() + jump_poly_stage_words<W>()];
+    const uint32_t per_task = M * parts;
+    const uint32_t ti = blockIdx.x / per_task, rem = blockIdx.x - ti * per_task;
+    const uint32_t t = rem / parts, part = rem - t * parts;
+    const JumpTask task = tasks ? tasks[ti] : one;
+    uint8_t* state = uniform(task.state);
+    const StateHeader* h = reinterpret_cast<const StateHeader*>(state);
+    const int k = (int)uniform(h->pos / M);  // words of every lane already consumed
+    const int max_deg = (int)uniform(task.max_deg);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int last_b = (k + max_deg) / N;
+    const int b0 = part_start((int)part, (int)parts, last_b + 1, ratio);
+    const int b1 = part_start((int)part + 1, (int)parts, last_b + 1, ratio);
+
+    const W* gwin = reinterpret_cast<const W*>(state + kHeaderBytes);
+    for (int j = tid; j < N; j += nthr) buf[j] = gwin[(size_t)j * M + t];
+    uint64_t* spoly = reinterpret_cast<uint64_t*>(buf + RW + jump_pad_words<N>());
+    const uint64_t* src = uniform(task.poly) + (size_t)task.lane_stride * t;
+    for (int i = tid; i <= (max_deg >> 6); i += nthr) spoly[i] = src[i];
+    __syncthreads();
+    // bare twists up to block b0, alternating between the two halves of the window
+    for (int i = 0; i < b0; ++i) {
+        const W* a = buf + (i & 1) * N;
+        raw_twist_rows<P>(a, buf + N - (i & 1) * N, 1, 0, tid, nthr);
+        __syncthreads();
+    }
+    if (b0 & 1) {  // block b0 sits in the upper half: move it down
+        for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];
+        __syncthreads();
+    }
+
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    if (b0 < b1) {
+        raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
+        __syncthreads();
+        derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+        __syncthreads();
+        for (int b = b0;; ++b) {
+            accumulate_block4<W, N, true>(acc, buf, 2 * N, spoly, k, b, max_deg, lane, wave, WPL);
+            if (b + 1 == b1) break;
+            __syncthreads();
+            for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
+            __syncthreads();
+            raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
+            __syncthreads();
+            derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = lane + 64 * s;
+        if (j < N) buf[wave * N + j] = acc[s];
+    }
+    __syncthreads();
+    W* dst = partial + ((size_t)(ti * M + t) * parts + part) * N;
+    for (int j = tid; j < N; j += nthr) {
+        W v = buf[j];
+#pragma unroll
+        for (int q = 1; q < WPL; ++q) v = xorw(v, buf[q * N + j]);
+        dst[j] = v;
+    }
+}
+
+// XOR of a lane jump's parts into lane t's window of the state, and the
+// position fix of finalize_jump_pos (by the workgroup of lane 0). One
+// workgroup per (task, lane). Tasks that carry a completion flag do not come
+// here: no workgroup of a task knows when the task's other lanes are done.
+template <class W, int N>
+__global__ __launch_bounds__(256) void reduce_jump_parts(const JumpTask* tasks, JumpTask one, uint32_t M,
+                                                         uint32_t parts, const W* partial) {
+    const uint32_t ti = blockIdx.x / M, t = blockIdx.x - ti * M;
+    const JumpTask task = tasks ? tasks[ti] : one;
+    W* gwin = reinterpret_cast<W*>(task.state + kHeaderBytes);
+    const W* src = partial + (size_t)blockIdx.x * parts * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        W v = src[j];
+        for (uint32_t q = 1; q < parts; ++q) v = xorw(v, src[(size_t)q * N + j]);
+        gwin[(size_t)j * M + t] = v;
+    }
+    if (t == 0 && threadIdx.x == 0) {
+        StateHeader* h = reinterpret_cast<StateHeader*>(task.state);
+        h->pos = h->pos % M;
+    }
+}
+
 // Jumps of one state's copies by different distances (the chunks of a split
 // call): every copy starts from the same window, so lane t's raw sequence is
 // the same for all of them. One workgroup per (lane t, CPW copies): the raw
@@ -1696,8 +1831,56 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
     return hipGetLastError();
 }
 
+#ifndef VMT_JUMP_PARTS_MAX
+#define VMT_JUMP_PARTS_MAX 8
+#endif
+#ifndef VMT_JUMP_PARTS_WGS
+#define VMT_JUMP_PARTS_WGS 512
+#endif
+
+uint32_t jump_parts(uint32_t variant, uint32_t M, uint64_t count) {
+    // MT jumps of up to 256 lanes (one 1,024-thread workgroup each) leave most
+    // compute units idle or one lane jump per unit: split each lane's blocks
+    // over up to 8 workgroups, so that about 512 of them (two per compute unit)
+    // run. SFMT regenerates its rows by a serial chain, which a later part
+    // would have to rerun from the start.
+    if (variant != kMT32 && variant != kMT64) return 1;
+    const uint64_t lanes = count * M;
+    if (lanes == 0 || lanes > 256) return 1;
+    uint32_t parts = 1;
+    while (parts < VMT_JUMP_PARTS_MAX && lanes * parts * 2 <= VMT_JUMP_PARTS_WGS) parts *= 2;
+    return parts;
+}
+
+size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
+    const uint32_t parts = jump_parts(variant, M, count);
+    if (parts == 1) return 0;
+    const size_t win = variant == kMT32 ? 624 * 4 : 312 * 8;  // one lane's window
+    return (size_t)count * M * parts * win;
+}
+
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
-                       hipStream_t stream) {
+                       hipStream_t stream, void* d_parts) {
+    const uint32_t parts = d_parts ? jump_parts(variant, M, count) : 1;
+    if (parts > 1) {
+        const dim3 grid(count * M * parts), block(16 * 64), rgrid(count * M);
+        if (variant == kMT32) {
+            jump_part_kernel<MT32P, 16><<<grid, block, 0, stream>>>(d_tasks, one, M, parts,
+                                                                   static_cast<uint32_t*>(d_parts), VMT_PART_RATIO_MT32);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            reduce_jump_parts<uint32_t, 624><<<rgrid, 256, 0, stream>>>(d_tasks, one, M, parts,
+                                                                       static_cast<const uint32_t*>(d_parts));
+        } else {
+            jump_part_kernel<MT64P, 16><<<grid, block, 0, stream>>>(d_tasks, one, M, parts,
+                                                                   static_cast<uint64_t*>(d_parts), VMT_PART_RATIO_MT64);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            reduce_jump_parts<uint64_t, 312><<<rgrid, 256, 0, stream>>>(d_tasks, one, M, parts,
+                                                                       static_cast<const uint64_t*>(d_parts));
+        }
+        return hipGetLastError();
+    }
     // Up to 1024 lanes: grouped accumulation, one lane per workgroup (40 KB of
     // LDS) and WPL wavefronts per lane, each summing a slice of the
     // coefficients: 16 for up to 256 lanes (one workgroup of 1024 threads per
@@ -1738,7 +1921,7 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
 
 
 hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src, const JumpTask* d_tasks,
-                             const JumpTask& one, uint32_t count, hipStream_t stream) {
+                             const JumpTask& one, uint32_t count, hipStream_t stream, void* d_parts) {
     // Few lanes: each lane jump on its own, sliced over wavefronts. More: the
     // copies share each lane's raw rows, CPW copies per workgroup (fewer when
     // that leaves under 512 workgroups). States of fewer than 16 words (SFMT607,
@@ -1746,7 +1929,7 @@ hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src,
     // barriers of a wide workgroup cost more than regenerating the rows.
     const uint64_t lanes = (uint64_t)count * M;
     if (lanes <= kSplitSharedLanes || words_per_lane(variant) < 16)
-        return launch_jump(variant, M, d_tasks, one, count, stream);
+        return launch_jump(variant, M, d_tasks, one, count, stream, d_parts);
     int cpw = 16;
     while (cpw > 4 && (uint64_t)M * ((count + cpw - 1) / cpw) < 512) cpw /= 2;
     const dim3 grid(M * ((count + cpw - 1) / cpw)), block(cpw * 64);

@@ -30,14 +30,21 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
                        const uint64_t* d_lane_polys, uint32_t max_deg, hipStream_t stream);
 
 // Jump `count` states (all of one variant and M), then fix their positions.
+// d_parts: device scratch of jump_parts_bytes(variant, M, count) bytes, or
+// nullptr. With it, MT jumps of few lanes split each lane's sum over several
+// workgroups (partial windows in d_parts, XORed by a second launch); the
+// scratch is in use until the launches have run. Tasks with a completion flag
+// need d_parts == nullptr.
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
-                       hipStream_t stream);
+                       hipStream_t stream, void* d_parts = nullptr);
+uint32_t jump_parts(uint32_t variant, uint32_t M, uint64_t count);       // workgroups per lane jump
+size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);   // 0: no scratch needed
 
 // Jump `count` copies of one state, each by its own polynomial (the chunks of
 // a split call), then fix their positions. d_src holds the window all copies
-// start from and is not one of them.
+// start from and is not one of them. d_parts as for launch_jump.
 hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src, const JumpTask* d_tasks,
-                             const JumpTask& one, uint32_t count, hipStream_t stream);
+                             const JumpTask& one, uint32_t count, hipStream_t stream, void* d_parts = nullptr);
 
 // Generate `len` elements from one state into d_out with `lpw` lanes per
 // workgroup (lpw divides M; lpw == M uses one workgroup).
