@@ -426,7 +426,7 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t off_jt = off_bt + (C * sizeof(vmt::BatchTask) + 255) / 256 * 256;
     const size_t off_ctr = off_jt + ((C - 1) * sizeof(vmt::JumpTask) + 255) / 256 * 256;
     const size_t off_parts = off_ctr + 256;
-    const size_t parts_bytes = vmt::jump_parts_bytes(info.variant, M, C - 1);
+    const size_t parts_bytes = vmt::split_jump_parts_bytes(info.variant, M, C - 1);
     const size_t total = off_parts + parts_bytes;
     uint8_t* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, total, stream);

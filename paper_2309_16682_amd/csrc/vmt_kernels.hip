@@ -1554,17 +1554,22 @@ __global__ __launch_bounds__(WPL * 64) void jump_part_kernel(const JumpTask* tas
 // position fix of finalize_jump_pos (by the workgroup of lane 0). One
 // workgroup per (task, lane). Tasks that carry a completion flag do not come
 // here: no workgroup of a task knows when the task's other lanes are done.
-template <class W, int N>
+// PARTS is a compile-time count, so that a thread's loads of all parts are in
+// flight together.
+template <class W, int N, int PARTS>
 __global__ __launch_bounds__(256) void reduce_jump_parts(const JumpTask* tasks, JumpTask one, uint32_t M,
-                                                         uint32_t parts, const W* partial) {
+                                                         const W* partial) {
     const uint32_t ti = blockIdx.x / M, t = blockIdx.x - ti * M;
     const JumpTask task = tasks ? tasks[ti] : one;
     W* gwin = reinterpret_cast<W*>(task.state + kHeaderBytes);
-    const W* src = partial + (size_t)blockIdx.x * parts * N;
+    const W* src = partial + (size_t)blockIdx.x * PARTS * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        W v = src[j];
-        for (uint32_t q = 1; q < parts; ++q) v = xorw(v, src[(size_t)q * N + j]);
-        gwin[(size_t)j * M + t] = v;
+        W v[PARTS];
+#pragma unroll
+        for (int q = 0; q < PARTS; ++q) v[q] = src[(size_t)q * N + j];
+#pragma unroll
+        for (int q = 1; q < PARTS; ++q) v[0] = xorw(v[0], v[q]);
+        gwin[(size_t)j * M + t] = v[0];
     }
     if (t == 0 && threadIdx.x == 0) {
         StateHeader* h = reinterpret_cast<StateHeader*>(task.state);
@@ -1633,6 +1638,87 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
         for (int s = 0; s < S; ++s) {
             const int j = lane + 64 * s;
             if (j < N) gdst[(size_t)j * M + t] = acc[s];
+        }
+    }
+}
+
+// The shared-row split jump with each lane's blocks split over `parts`
+// workgroups (MT): workgroup (copy group, lane t, part p) regenerates lane
+// t's raw rows for blocks [b0, b1) once, after b0 bare twists, and wavefront
+// w sums copy w's polynomial over them, writing its partial window to
+// `partial` for reduce_jump_parts. The parts of a copy group take the same
+// block boundaries (all compute them from the group's highest degree). Few
+// copies per lane then still fill the chip, while the rows are derived once
+// per block for all copies of the workgroup.
+template <class P, int CPW>
+__global__ __launch_bounds__(CPW * 64) void split_part_jump_kernel(const uint8_t* src, const JumpTask* tasks,
+                                                                   uint32_t count, uint32_t M, uint32_t parts,
+                                                                   typename P::W* partial, float ratio) {
+    using W = typename P::W;
+    constexpr int N = P::N;
+    constexpr int S = (N + 63) / 64;
+    constexpr int RW = jump_row_words<N, true>();
+    __shared__ __attribute__((aligned(16))) W buf[RW + jump_pad_words<N>()];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t part = blockIdx.x % parts, rest = blockIdx.x / parts;
+    const uint32_t t = rest % M;  // lane of the state
+    const uint32_t first = (rest / M) * CPW;
+    const uint32_t mine = first + w;
+    const bool active = mine < count;
+    const StateHeader* h = reinterpret_cast<const StateHeader*>(src);
+    const int k = (int)uniform((uint32_t)(h->pos / M));  // words of every lane already consumed
+    int max_deg = 0;
+    for (uint32_t i = first; i < first + CPW && i < count; ++i) max_deg = max(max_deg, (int)tasks[i].max_deg);
+    max_deg = (int)uniform((uint32_t)max_deg);
+    const uint64_t* poly = nullptr;
+    int my_deg = -1;
+    if (active) {
+        poly = uniform(tasks[mine].poly);
+        my_deg = (int)uniform(tasks[mine].max_deg);
+    }
+    const int last_b = (k + max_deg) / N;
+    const int b0 = part_start((int)part, (int)parts, last_b + 1, ratio);
+    const int b1 = part_start((int)part + 1, (int)parts, last_b + 1, ratio);
+
+    const W* gsrc = reinterpret_cast<const W*>(src + kHeaderBytes);
+    for (int j = tid; j < N; j += nthr) buf[j] = gsrc[(size_t)j * M + t];
+    __syncthreads();
+    for (int i = 0; i < b0; ++i) {  // bare twists up to block b0, between the two halves of the window
+        raw_twist_rows<P>(buf + (i & 1) * N, buf + N - (i & 1) * N, 1, 0, tid, nthr);
+        __syncthreads();
+    }
+    if (b0 & 1) {
+        for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];
+        __syncthreads();
+    }
+    W acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = zero_w<W>();
+    if (b0 < b1) {
+        raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
+        __syncthreads();
+        derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+        __syncthreads();
+        for (int b = b0;; ++b) {
+            if (active) accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1);
+            if (b + 1 == b1) break;
+            __syncthreads();
+            for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
+            __syncthreads();
+            raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
+            __syncthreads();
+            derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+            __syncthreads();
+        }
+    }
+    if (active) {
+        W* dst = partial + ((size_t)(mine * M + t) * parts + part) * N;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = lane + 64 * s;
+            if (j < N) dst[j] = acc[s];
         }
     }
 }
@@ -1838,6 +1924,27 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
 #define VMT_JUMP_PARTS_WGS 512
 #endif
 
+#define VMT_PARTS_SWITCH(PS, ...)                                 \
+    switch (PS) {                                                 \
+        case 2: { constexpr int PP = 2; __VA_ARGS__; break; }     \
+        case 4: { constexpr int PP = 4; __VA_ARGS__; break; }     \
+        case 8: { constexpr int PP = 8; __VA_ARGS__; break; }     \
+        default: { constexpr int PP = 16; __VA_ARGS__; break; }   \
+    }
+
+// XOR the parts of `count` tasks' lane jumps into their states (parts: 2, 4, 8 or 16)
+static void launch_reduce_parts(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one,
+                                uint32_t count, uint32_t parts, const void* d_parts, hipStream_t stream) {
+    const dim3 grid(count * M), block(256);
+    if (variant == kMT32) {
+        VMT_PARTS_SWITCH(parts, (reduce_jump_parts<uint32_t, 624, PP><<<grid, block, 0, stream>>>(
+                                    d_tasks, one, M, static_cast<const uint32_t*>(d_parts))))
+    } else {
+        VMT_PARTS_SWITCH(parts, (reduce_jump_parts<uint64_t, 312, PP><<<grid, block, 0, stream>>>(
+                                    d_tasks, one, M, static_cast<const uint64_t*>(d_parts))))
+    }
+}
+
 uint32_t jump_parts(uint32_t variant, uint32_t M, uint64_t count) {
     // MT jumps of up to 256 lanes (one 1,024-thread workgroup each) leave most
     // compute units idle or one lane jump per unit: split each lane's blocks
@@ -1859,26 +1966,49 @@ size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
     return (size_t)count * M * parts * win;
 }
 
+#ifndef VMT_SPLIT_SHARE_PARTS
+#define VMT_SPLIT_SHARE_PARTS 1
+#endif
+// A shared-row block carries the sums of up to 16 copies, so a bare twist
+// costs far less of it than of a sliced block: near-equal parts.
+#ifndef VMT_SHARE_RATIO
+#define VMT_SHARE_RATIO 0.005f
+#endif
+
+uint32_t split_share_parts(uint32_t variant, uint32_t M, uint64_t count) {
+    // MT split jumps whose copies, 16 per workgroup, give each lane fewer than
+    // 512 workgroups: split every lane's blocks over up to 16 of them, when
+    // that reaches at least 256 workgroups (one per compute unit). Fewer
+    // lanes and copies run faster sliced (jump_part_kernel).
+    if (!VMT_SPLIT_SHARE_PARTS || (variant != kMT32 && variant != kMT64)) return 1;
+    const uint64_t wgs = (uint64_t)M * ((count + 15) / 16);
+    uint32_t parts = 1;
+    while (parts < 16 && wgs * parts * 2 <= 512) parts *= 2;
+    return wgs * parts >= 256 ? parts : 1;
+}
+
+size_t split_jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
+    const size_t win = variant == kMT32 ? 624 * 4 : 312 * 8;
+    const uint32_t sp = split_share_parts(variant, M, count);
+    if (sp > 1) return (size_t)count * M * sp * win;
+    if ((uint64_t)count * M <= 1024) return jump_parts_bytes(variant, M, count);
+    return 0;
+}
+
 hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one, uint32_t count,
                        hipStream_t stream, void* d_parts) {
     const uint32_t parts = d_parts ? jump_parts(variant, M, count) : 1;
     if (parts > 1) {
-        const dim3 grid(count * M * parts), block(16 * 64), rgrid(count * M);
-        if (variant == kMT32) {
+        const dim3 grid(count * M * parts), block(16 * 64);
+        if (variant == kMT32)
             jump_part_kernel<MT32P, 16><<<grid, block, 0, stream>>>(d_tasks, one, M, parts,
                                                                    static_cast<uint32_t*>(d_parts), VMT_PART_RATIO_MT32);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            reduce_jump_parts<uint32_t, 624><<<rgrid, 256, 0, stream>>>(d_tasks, one, M, parts,
-                                                                       static_cast<const uint32_t*>(d_parts));
-        } else {
+        else
             jump_part_kernel<MT64P, 16><<<grid, block, 0, stream>>>(d_tasks, one, M, parts,
                                                                    static_cast<uint64_t*>(d_parts), VMT_PART_RATIO_MT64);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            reduce_jump_parts<uint64_t, 312><<<rgrid, 256, 0, stream>>>(d_tasks, one, M, parts,
-                                                                       static_cast<const uint64_t*>(d_parts));
-        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        launch_reduce_parts(variant, M, d_tasks, one, count, parts, d_parts, stream);
         return hipGetLastError();
     }
     // Up to 1024 lanes: grouped accumulation, one lane per workgroup (40 KB of
@@ -1928,6 +2058,20 @@ hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src,
     // SFMT1279) keep a row per lane jump: their blocks are so short that the
     // barriers of a wide workgroup cost more than regenerating the rows.
     const uint64_t lanes = (uint64_t)count * M;
+    const uint32_t sp = d_parts ? split_share_parts(variant, M, count) : 1;
+    if (sp > 1) {
+        const dim3 grid((uint32_t)(M * ((count + 15) / 16) * sp)), block(16 * 64);
+        if (variant == kMT32)
+            split_part_jump_kernel<MT32P, 16><<<grid, block, 0, stream>>>(
+                d_src, d_tasks, count, M, sp, static_cast<uint32_t*>(d_parts), VMT_SHARE_RATIO);
+        else
+            split_part_jump_kernel<MT64P, 16><<<grid, block, 0, stream>>>(
+                d_src, d_tasks, count, M, sp, static_cast<uint64_t*>(d_parts), VMT_SHARE_RATIO);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        launch_reduce_parts(variant, M, d_tasks, one, count, sp, d_parts, stream);
+        return hipGetLastError();
+    }
     if (lanes <= kSplitSharedLanes || words_per_lane(variant) < 16)
         return launch_jump(variant, M, d_tasks, one, count, stream, d_parts);
     int cpw = 16;

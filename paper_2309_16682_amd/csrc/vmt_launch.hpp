@@ -39,6 +39,7 @@ hipError_t launch_jump(uint32_t variant, uint32_t M, const JumpTask* d_tasks, co
                        hipStream_t stream, void* d_parts = nullptr);
 uint32_t jump_parts(uint32_t variant, uint32_t M, uint64_t count);       // workgroups per lane jump
 size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);   // 0: no scratch needed
+size_t split_jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);  // d_parts of launch_split_jump
 
 // Jump `count` copies of one state, each by its own polynomial (the chunks of
 // a split call), then fix their positions. d_src holds the window all copies

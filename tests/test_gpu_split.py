@@ -79,6 +79,9 @@ CASES = [
     (SFMT, 4, vmt.VMT_OUT_U32, 4, 300.7, 5),
     (SFMT, 64, vmt.VMT_OUT_F32, 4, 20.2, 1000),
     (SFMT, 2, vmt.VMT_OUT_U32, 4, 4200.1, 9),
+    # MT copies whose lanes' blocks are split over 2 workgroups (16 copies per workgroup; 4, 8 and 16 above)
+    (MT32, 16, vmt.VMT_OUT_U32, 4, 150.6, 11),
+    (MT64, 8, vmt.VMT_OUT_U64, 4, 260.4, 5),
 ]
 
 
