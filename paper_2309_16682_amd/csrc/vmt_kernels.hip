@@ -1036,14 +1036,18 @@ __device__ __forceinline__ void accumulate_block(W (&acc)[(N + 63) / 64], const 
 // coefficient range (XOR is linear: the parts' sums add up to the block's).
 // PADDED: the buffer extends jump_pad_words<N>() words past the last derived
 // row, so the reads of the last partial wavefront row need no range test
-// (lanes past the window read words they never store).
+// (lanes past the window read words they never store). [clo, chi) further
+// limits the coefficients taken (a part of a lane jump split by coefficient
+// range).
 template <class W, int N, bool PADDED = false>
 __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const W* rows, int rstride,
                                                   const uint64_t* poly, int k, int b, int max_deg, int lane,
-                                                  int part, int parts) {
+                                                  int part, int parts, int clo = 0, int chi = 1 << 30) {
     constexpr int S = (N + 63) / 64;
     int lo = b * N - k, hi = (b + 1) * N - k;  // coefficient range for this block
+    if (lo < clo) lo = clo;
     if (lo < 0) lo = 0;
+    if (hi > chi) hi = chi;
     if (hi > max_deg + 1) hi = max_deg + 1;
     if (lo >= hi) return;
     if (parts > 1) {
@@ -1444,13 +1448,13 @@ __global__ __launch_bounds__(G * WPL * 64) void jump_kernel(const JumpTask* task
 #define VMT_PART_RATIO_MT64 0.1f
 #endif
 
-// First block of part p of `parts` over the nb blocks of a lane jump. A part
-// that starts at block b first twists its raw row b times without summing, so
-// later parts get fewer blocks: with r the cost of a bare twist relative to a
-// summed block, part p's share is q^p (q = 1 - r) of the first part's, and
-// each part's twists plus sums come to about the same time. Every workgroup
-// of a lane jump evaluates this in the same order, so the parts tile the
-// blocks exactly.
+// First coefficient of part p of `parts` over the nb coefficients of a lane
+// jump. A part whose first coefficient lies in block b first twists its raw
+// row b times without summing, so later parts get fewer coefficients: with r
+// the cost of a bare twist relative to summing a block, part p's share is q^p
+// (q = 1 - r) of the first part's, and each part's twists plus sums come to
+// about the same time. Every workgroup of a lane jump evaluates this in the
+// same order, so the parts tile the coefficients exactly.
 __device__ __forceinline__ int part_start(int p, int parts, int nb, float r) {
     const float q = 1.0f - r;
     float c = 0.0f, total = 0.0f, w = 1.0f;
@@ -1465,12 +1469,12 @@ __device__ __forceinline__ int part_start(int p, int parts, int nb, float r) {
 }
 
 // One part of an MT lane jump (jumps of few lanes). The sum over g's
-// coefficients is linear, so it splits over ranges of blocks: workgroup
-// (task, lane t, part p) sums blocks [b0, b1) of lane t's raw sequence, its
-// WPL wavefronts slicing each block's groups as in the sliced jump, and
-// writes the partial window (N contiguous words) to `partial`. Before its
-// first block it twists the lane's row from the window b0 times (two N-word
-// halves of LDS in turn, one barrier per block). A separate launch XORs the
+// coefficients is linear, so it splits over coefficient ranges: workgroup
+// (task, lane t, part p) sums coefficients [c0, c1) over blocks [b0, b1) of
+// lane t's raw sequence, its WPL wavefronts slicing each block's groups as in
+// the sliced jump, and writes the partial window (N contiguous words) to
+// `partial`. Before its first block it twists the lane's row from the window
+// b0 times (two N-word halves of LDS in turn, one barrier per block). A separate launch XORs the
 // parts into the state (reduce_jump_parts). All parts read the window and the
 // position before any of them is replaced.
 template <class P, int WPL>
@@ -1493,9 +1497,10 @@ __global__ __launch_bounds__(WPL * 64) void jump_part_kernel(const JumpTask* tas
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int last_b = (k + max_deg) / N;
-    const int b0 = part_start((int)part, (int)parts, last_b + 1, ratio);
-    const int b1 = part_start((int)part + 1, (int)parts, last_b + 1, ratio);
+    // coefficients [c0, c1) of the lane's polynomial, in blocks [b0, b1)
+    const int c0 = part_start((int)part, (int)parts, max_deg + 1, ratio);
+    const int c1 = part_start((int)part + 1, (int)parts, max_deg + 1, ratio);
+    const int b0 = (c0 + k) / N, b1 = c1 > c0 ? (c1 - 1 + k) / N + 1 : b0;
 
     const W* gwin = reinterpret_cast<const W*>(state + kHeaderBytes);
     for (int j = tid; j < N; j += nthr) buf[j] = gwin[(size_t)j * M + t];
@@ -1523,7 +1528,7 @@ __global__ __launch_bounds__(WPL * 64) void jump_part_kernel(const JumpTask* tas
         derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
         __syncthreads();
         for (int b = b0;; ++b) {
-            accumulate_block4<W, N, true>(acc, buf, 2 * N, spoly, k, b, max_deg, lane, wave, WPL);
+            accumulate_block4<W, N, true>(acc, buf, 2 * N, spoly, k, b, max_deg, lane, wave, WPL, c0, c1);
             if (b + 1 == b1) break;
             __syncthreads();
             for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
@@ -1642,12 +1647,13 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
     }
 }
 
-// The shared-row split jump with each lane's blocks split over `parts`
+// The shared-row split jump with each lane's coefficients split over `parts`
 // workgroups (MT): workgroup (copy group, lane t, part p) regenerates lane
-// t's raw rows for blocks [b0, b1) once, after b0 bare twists, and wavefront
-// w sums copy w's polynomial over them, writing its partial window to
-// `partial` for reduce_jump_parts. The parts of a copy group take the same
-// block boundaries (all compute them from the group's highest degree). Few
+// t's raw rows for the blocks of coefficients [c0, c1) once, after bare
+// twists up to the first, and wavefront w sums copy w's polynomial over them,
+// writing its partial window to `partial` for reduce_jump_parts. The parts of
+// a copy group take the same boundaries (all compute them from the group's
+// highest degree). Few
 // copies per lane then still fill the chip, while the rows are derived once
 // per block for all copies of the workgroup.
 template <class P, int CPW>
@@ -1678,9 +1684,9 @@ __global__ __launch_bounds__(CPW * 64) void split_part_jump_kernel(const uint8_t
         poly = uniform(tasks[mine].poly);
         my_deg = (int)uniform(tasks[mine].max_deg);
     }
-    const int last_b = (k + max_deg) / N;
-    const int b0 = part_start((int)part, (int)parts, last_b + 1, ratio);
-    const int b1 = part_start((int)part + 1, (int)parts, last_b + 1, ratio);
+    const int c0 = part_start((int)part, (int)parts, max_deg + 1, ratio);
+    const int c1 = part_start((int)part + 1, (int)parts, max_deg + 1, ratio);
+    const int b0 = (c0 + k) / N, b1 = c1 > c0 ? (c1 - 1 + k) / N + 1 : b0;
 
     const W* gsrc = reinterpret_cast<const W*>(src + kHeaderBytes);
     for (int j = tid; j < N; j += nthr) buf[j] = gsrc[(size_t)j * M + t];
@@ -1702,7 +1708,7 @@ __global__ __launch_bounds__(CPW * 64) void split_part_jump_kernel(const uint8_t
         derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
         __syncthreads();
         for (int b = b0;; ++b) {
-            if (active) accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1);
+            if (active) accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1, c0, c1);
             if (b + 1 == b1) break;
             __syncthreads();
             for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
@@ -1929,10 +1935,11 @@ hipError_t launch_init(uint32_t variant, uint32_t M, const InitTask* d_tasks, co
         case 2: { constexpr int PP = 2; __VA_ARGS__; break; }     \
         case 4: { constexpr int PP = 4; __VA_ARGS__; break; }     \
         case 8: { constexpr int PP = 8; __VA_ARGS__; break; }     \
-        default: { constexpr int PP = 16; __VA_ARGS__; break; }   \
+        case 16: { constexpr int PP = 16; __VA_ARGS__; break; }   \
+        default: { constexpr int PP = 32; __VA_ARGS__; break; }   \
     }
 
-// XOR the parts of `count` tasks' lane jumps into their states (parts: 2, 4, 8 or 16)
+// XOR the parts of `count` tasks' lane jumps into their states (parts: 2, 4, 8, 16 or 32)
 static void launch_reduce_parts(uint32_t variant, uint32_t M, const JumpTask* d_tasks, const JumpTask& one,
                                 uint32_t count, uint32_t parts, const void* d_parts, hipStream_t stream) {
     const dim3 grid(count * M), block(256);
@@ -1974,6 +1981,12 @@ size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
 #ifndef VMT_SHARE_RATIO
 #define VMT_SHARE_RATIO 0.005f
 #endif
+#ifndef VMT_SHARE_PARTS_MAX
+#define VMT_SHARE_PARTS_MAX 16
+#endif
+#ifndef VMT_SHARE_WGS
+#define VMT_SHARE_WGS 512
+#endif
 
 uint32_t split_share_parts(uint32_t variant, uint32_t M, uint64_t count) {
     // MT split jumps whose copies, 16 per workgroup, give each lane fewer than
@@ -1983,7 +1996,7 @@ uint32_t split_share_parts(uint32_t variant, uint32_t M, uint64_t count) {
     if (!VMT_SPLIT_SHARE_PARTS || (variant != kMT32 && variant != kMT64)) return 1;
     const uint64_t wgs = (uint64_t)M * ((count + 15) / 16);
     uint32_t parts = 1;
-    while (parts < 16 && wgs * parts * 2 <= 512) parts *= 2;
+    while (parts < VMT_SHARE_PARTS_MAX && wgs * parts * 2 <= VMT_SHARE_WGS) parts *= 2;
     return wgs * parts >= 256 ? parts : 1;
 }
 
