@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "aac664d8f3bdd5a108108b8302347cb2edc3fdcc55f55e8fab1baaf49941907c",
+    "kernel_fingerprint": "b74a8ad19e4613d3b5503592861b13d4d41b3942f5ce9d8da97cc55188e067c3",
     "shapes": {
-        (512, 16, 2): (878101717, 96283548245),
-        (512, 8, 2): (878114475, 96283547872),
-        (256, 16, 2): (878140373, 96283547904),
-        (256, 8, 3): (878355456, 96283564235),
-        (960, 16, 2): (878076971, 96283549803),
+        (512, 16, 2): (878073600, 96283547968),
+        (512, 8, 2): (878163285, 96283547872),
+        (256, 16, 2): (878287573, 96283547861),
+        (256, 8, 3): (878354261, 96283564267),
+        (960, 16, 2): (878120619, 96283549077),
     },
 }
 
