@@ -28,38 +28,39 @@ def ctx():
     vmt.vmt_ctx_destroy(c)
 
 
-def make_states(ctx, n):
-    pool = torch.empty(n * vmt.vmt_state_bytes(MT64, M), dtype=torch.uint8, device="cuda")
-    sb = vmt.vmt_state_bytes(MT64, M)
+def make_states(ctx, n, variant=MT64, lanes=M):
+    sb = vmt.vmt_state_bytes(variant, lanes)
+    pool = torch.empty(n * sb, dtype=torch.uint8, device="cuda")
     states = [pool[i * sb : (i + 1) * sb] for i in range(n)]
     for i, st in enumerate(states):
-        vmt.vmt_init_genrand(ctx, MT64, i + 1, M, st)
+        vmt.vmt_init_genrand(ctx, variant, i + 1, lanes, st)
     torch.cuda.synchronize()
     return pool, states
 
 
-def small_trace(n_states, seconds, rate, seed):
-    tr = serving_trace(seconds, rate_per_s=rate, n_states=n_states, min_bytes=8, max_bytes=64 << 10, elem_bytes=8,
-                       jump_fraction=0.15, kmin=32, kmax=80, seed=seed)
+def small_trace(n_states, seconds, rate, seed, elem_bytes=8):
+    tr = serving_trace(seconds, rate_per_s=rate, n_states=n_states, min_bytes=8, max_bytes=64 << 10,
+                       elem_bytes=elem_bytes, jump_fraction=0.15, kmin=32, kmax=80, seed=seed)
     return [(r.t_arrival, r.state, 0 if r.kind == "gen" else 1, r.nelem if r.kind == "gen" else 0, r.k) for r in tr]
 
 
-def check_against_oracle(reqs, res, arena):
-    gJ = golden_io.lane_poly(MT64, M)
+def check_against_oracle(reqs, res, arena, variant=MT64, lanes=M):
+    gJ = golden_io.lane_poly(variant, lanes)
+    eb, dt = (8, np.uint64) if variant == MT64 else (4, np.uint32)
     host = arena.cpu().numpy()
     by_state = {}
     for i, r in enumerate(reqs):
         by_state.setdefault(r[1], []).append(i)
     for st, idx in by_state.items():
-        ref = O.VStream(MT64, M, O.seed_state(MT64, st + 1), gJ)
+        ref = O.VStream(variant, lanes, O.seed_state(variant, st + 1), gJ)
         for i in sorted(idx, key=lambda j: (reqs[j][0], j)):
             t, _, kind, count, k = reqs[i]
             assert res[i]["status"] == 0
             if kind == 1:
-                ref.jump(pow2_poly(MT64, k))
+                ref.jump(pow2_poly(variant, k))
             else:
                 off = int(res[i]["out_offset"])
-                got = host[off : off + 8 * count].view(np.uint64)
+                got = host[off : off + eb * count].view(dt)
                 np.testing.assert_array_equal(got, ref.generate(count), err_msg=f"request {i} state {st}")
 
 
@@ -86,6 +87,25 @@ def test_results_in_the_mix_equal_each_state_alone(ctx, mode, realtime, chunk):
         for a, b in zip(idx, idx[1:]):
             assert res[b]["t_admit"] >= res[a]["t_done"]
     check_against_oracle(reqs, res, arena)
+
+
+@pytest.mark.parametrize("chunk", [300, 2000])
+def test_split_requests_of_v_mt19937_32(ctx, chunk):
+    # V-MT19937-32, M = 16, large requests split into chunks (up to 31 jumped copies per request)
+    n_states, lanes = 12, 16
+    reqs = small_trace(n_states, 0.05, 6000.0, seed=21 + chunk, elem_bytes=4)
+    say(f"case serving MT32 split chunk={chunk} requests={len(reqs)}")
+    total = sum(4 * r[3] for r in reqs) + 256 * len(reqs) + (1 << 20)
+    pool, states = make_states(ctx, n_states, vmt.VMT_MT32, lanes)
+    arena = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    srv = vmt.vmt_server_create(ctx, states, arena, total, total, vmt.VMT_OUT_U32, n_streams=4, mode=4 | 2,
+                                chunk_elems=chunk)
+    try:
+        res, _ = vmt.vmt_server_run(srv, reqs, realtime=False)
+    finally:
+        vmt.vmt_server_destroy(srv)
+    assert (res["status"] == 0).all()
+    check_against_oracle(reqs, res, arena, vmt.VMT_MT32, lanes)
 
 
 @pytest.mark.parametrize("mode", [2, 6])
