@@ -994,6 +994,17 @@ __device__ void raw_twist_rows_sfmt(const uint4* src, uint4* dst, int rows, int 
 __device__ __forceinline__ uint32_t xorw(uint32_t a, uint32_t b) { return a ^ b; }
 __device__ __forceinline__ uint64_t xorw(uint64_t a, uint64_t b) { return a ^ b; }
 __device__ __forceinline__ uint4 xorw(uint4 a, uint4 b) { return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w); }
+// a ^ b ^ c as one three-input bitwise operation per 32 bits (truth table 0x96)
+__device__ __forceinline__ uint32_t xorw3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint64_t xorw3(uint64_t a, uint64_t b, uint64_t c) {
+    return (uint64_t)xorw3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32 |
+           xorw3((uint32_t)a, (uint32_t)b, (uint32_t)c);
+}
+__device__ __forceinline__ uint4 xorw3(uint4 a, uint4 b, uint4 c) {
+    return make_uint4(xorw3(a.x, b.x, c.x), xorw3(a.y, b.y, c.y), xorw3(a.z, b.z, c.z), xorw3(a.w, b.w, c.w));
+}
 template <class W>
 __device__ __forceinline__ W zero_w() { return W(0); }
 template <>
@@ -1090,7 +1101,7 @@ __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const
                 for (int s = 0; s < S; ++s)
                     vb[s] = (PADDED || s < S - 1 || lane + 64 * s < N) ? sb[64 * s] : zero_w<W>();
 #pragma unroll
-                for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], xorw(va[s], vb[s]));
+                for (int s = 0; s < S; ++s) acc[s] = xorw3(acc[s], va[s], vb[s]);
             } else {
 #pragma unroll
                 for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], va[s]);
