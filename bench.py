@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "b74a8ad19e4613d3b5503592861b13d4d41b3942f5ce9d8da97cc55188e067c3",
+    "kernel_fingerprint": "cd49b42695187f1d22923cbaf0a351928ce409af0e82856f8b5f95b1e41b154c",
     "shapes": {
-        (512, 16, 2): (878073600, 96283547968),
-        (512, 8, 2): (878163285, 96283547872),
-        (256, 16, 2): (878287573, 96283547861),
-        (256, 8, 3): (878354261, 96283564267),
-        (960, 16, 2): (878120619, 96283549077),
+        (512, 16, 2): (878015616, 96283548000),
+        (512, 8, 2): (878085760, 96283547808),
+        (256, 16, 2): (878127872, 96283547829),
+        (256, 8, 3): (878318891, 96283564256),
+        (960, 16, 2): (878177280, 96283548821),
     },
 }
 
