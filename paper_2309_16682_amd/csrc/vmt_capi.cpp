@@ -63,7 +63,8 @@ struct DevPoly {
 struct SplitTable {
     std::vector<Words> host;
     std::vector<uint32_t> deg;
-    uint64_t* d = nullptr;
+    uint64_t* d = nullptr;      // cap slots of kPolyWords words
+    uint32_t* d_deg = nullptr;  // their degrees
     size_t cap = 0, uploaded = 0;
 };
 
@@ -383,10 +384,18 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
     if (T.cap < need) {
         const size_t cap = std::max<size_t>({need, 2 * T.cap, 16});
         uint64_t* d = nullptr;
+        uint32_t* dd = nullptr;
         hipError_t e = hipMalloc((void**)&d, cap * vmt::kPolyWords * 8);
         if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMalloc(split table): %s", hipGetErrorString(e));
+        e = hipMalloc((void**)&dd, cap * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(VMT_ENOMEM, "hipMalloc(split degrees): %s", hipGetErrorString(e));
+        }
         if (T.d) ctx->retired.push_back(T.d);
+        if (T.d_deg) ctx->retired.push_back(T.d_deg);
         T.d = d;
+        T.d_deg = dd;
         T.cap = cap;
         T.uploaded = 0;
     }
@@ -396,6 +405,9 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
             std::copy(T.host[c].begin(), T.host[c].begin() + std::min<size_t>(T.host[c].size(), vmt::kPolyWords),
                       buf.begin() + (c - T.uploaded) * vmt::kPolyWords);
         hipError_t e = hipMemcpy(T.d + T.uploaded * vmt::kPolyWords, buf.data(), buf.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(T.d_deg + T.uploaded, T.deg.data() + T.uploaded, (need - T.uploaded) * sizeof(uint32_t),
+                          hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
         T.uploaded = need;
     }
@@ -411,14 +423,16 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const uint64_t C = ceil_div(n, E);
     const size_t eb = out_elem_bytes(out_kind);
     const uint64_t* polys = nullptr;
-    std::vector<uint32_t> deg;
+    const uint32_t* d_deg = nullptr;
+    uint32_t deg0 = 0;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         SplitTable* T = nullptr;
         int st = split_table(ctx, info.variant, v, C - 1, &T);
         if (st) return st;
         polys = T->d;
-        deg.assign(T->deg.begin(), T->deg.begin() + (C - 1));
+        d_deg = T->d_deg;
+        deg0 = C > 1 ? T->deg[0] : 0u;
     }
     const size_t sb = vmt_state_bytes(info.variant, M);
     const size_t sbs = (sb + 255) / 256 * 256;
@@ -431,22 +445,16 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     uint8_t* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, total, stream);
     if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
-    std::vector<uint8_t> host(off_parts - off_bt, 0);
-    auto* bt = reinterpret_cast<vmt::BatchTask*>(host.data());
-    auto* jt = reinterpret_cast<vmt::JumpTask*>(host.data() + (off_jt - off_bt));
-    for (uint64_t c = 0; c < C; c++) {
-        uint8_t* st = c + 1 == C ? d_state : buf + c * sbs;  // copies for chunks 0 .. C-2, the state for the last
-        bt[c] = vmt::BatchTask{st, d_out + c * E * eb, c + 1 < C ? E : n - c * E, nullptr};
-        if (c) jt[c - 1] = vmt::JumpTask{st, polys + (c - 1) * vmt::kPolyWords, 0u, deg[c - 1], nullptr};
-    }
     auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
     auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
-    e = hipMemcpyAsync(buf + off_bt, host.data(), off_ctr - off_bt, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = vmt::launch_replicate(d_state, buf, (uint32_t)sb, sbs, (uint32_t)(C - 1), stream);
+    // copies for chunks 0 .. C-2, the state itself for the last; the task lists are written on the device
+    e = vmt::launch_split_setup(d_state, buf, (uint32_t)sb, sbs, (uint32_t)C, d_out, E, n, (uint32_t)eb, polys, d_deg,
+                                d_bt, d_jt, stream);
     // copy 0 is chunk 0: it is not jumped and holds the window every other chunk starts from
+    const vmt::JumpTask jt0{C > 2 ? buf + sbs : d_state, polys, 0u, deg0, nullptr};  // the first jump task, as written
     if (e == hipSuccess)
-        e = vmt::launch_split_jump(info.variant, M, buf, d_jt, jt[0], (uint32_t)(C - 1), stream,
+        e = vmt::launch_split_jump(info.variant, M, buf, d_jt, jt0, (uint32_t)(C - 1), stream,
                                    parts_bytes ? buf + off_parts : nullptr);
     if (e == hipSuccess) {
         if (vmt::is_sfmt(info.variant)) {
@@ -722,7 +730,10 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
             for (auto& kv : ctx->lanes[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->jumps[v]) (void)hipFree(kv.second.d);
             for (auto& kv : ctx->pow2_dev[v]) (void)hipFree(kv.second.d);
-            for (auto& kv : ctx->split[v]) (void)hipFree(kv.second.d);
+            for (auto& kv : ctx->split[v]) {
+                (void)hipFree(kv.second.d);
+                (void)hipFree(kv.second.d_deg);
+            }
             for (auto& kv : ctx->check[v]) (void)hipFree(kv.second.d);
         }
         for (void* p : ctx->retired) (void)hipFree(p);

@@ -921,11 +921,25 @@ __global__ void copy_states(const CopyTask* tasks, uint32_t bytes) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < bytes / 16; i += gridDim.x * blockDim.x) d[i] = s[i];
 }
 
-// Copy a whole state (header and window; `bytes` a multiple of 16) from src
-// to `count` slots spaced `stride` bytes apart.
-__global__ void replicate_state(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride) {
-    const uint4* s = reinterpret_cast<const uint4*>(src);
-    uint4* d = reinterpret_cast<uint4*>(dst + stride * blockIdx.y);
+// Set-up of a split call in one launch: the chunks' generation tasks, the
+// jump tasks of chunks 1 .. C-1 and the copies of the state (header and
+// window) that chunks 0 .. C-2 run on. Chunk c covers output elements
+// [c E, (c + 1) E), the last one the rest of n, and runs on copy c (the last
+// chunk on the state itself); chunk c >= 1 is jumped by slot c - 1 of `polys`
+// (degree deg[c - 1]). Workgroup (x, c) copies its share of copy c, and
+// thread 0 of workgroup (0, c) writes chunk c's tasks.
+__global__ void split_setup(const uint8_t* state, uint8_t* copies, uint32_t bytes, uint64_t stride, uint32_t C,
+                            uint8_t* out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* polys,
+                            const uint32_t* deg, BatchTask* bt, JumpTask* jt) {
+    const uint32_t c = blockIdx.y;
+    uint8_t* st = c + 1 == C ? const_cast<uint8_t*>(state) : copies + stride * c;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        bt[c] = BatchTask{st, out + (uint64_t)c * E * eb, c + 1 < C ? E : n - (uint64_t)c * E, nullptr};
+        if (c) jt[c - 1] = JumpTask{st, polys + (size_t)(c - 1) * kPolyWords, 0u, deg[c - 1], nullptr};
+    }
+    if (c + 1 == C) return;
+    const uint4* s = reinterpret_cast<const uint4*>(state);
+    uint4* d = reinterpret_cast<uint4*>(st);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < bytes / 16; i += gridDim.x * blockDim.x) d[i] = s[i];
 }
 
@@ -2286,11 +2300,13 @@ hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int o
     return hipGetLastError();
 }
 
-hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride, uint32_t count,
-                            hipStream_t stream) {
-    if (count == 0) return hipSuccess;
+hipError_t launch_split_setup(const uint8_t* d_state, uint8_t* d_copies, uint32_t bytes, uint64_t stride, uint32_t C,
+                              uint8_t* d_out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* d_polys,
+                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, hipStream_t stream) {
+    if (C == 0) return hipSuccess;
     const uint32_t per = (bytes / 16 + 255) / 256;
-    replicate_state<<<dim3(per < 64 ? per : 64, count), 256, 0, stream>>>(src, dst, bytes, stride);
+    split_setup<<<dim3(per < 64 ? per : 64, C), 256, 0, stream>>>(d_state, d_copies, bytes, stride, C, d_out, E, n, eb,
+                                                                  d_polys, d_deg, d_bt, d_jt);
     return hipGetLastError();
 }
 

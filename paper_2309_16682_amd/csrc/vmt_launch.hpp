@@ -41,6 +41,15 @@ uint32_t jump_parts(uint32_t variant, uint32_t M, uint64_t count);       // work
 size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);   // 0: no scratch needed
 size_t split_jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);  // d_parts of launch_split_jump
 
+// Set-up of a split call: C chunks of E elements (the last n - (C-1) E) of
+// eb bytes into d_out; generation tasks d_bt[C], jump tasks d_jt[C-1] (chunk
+// c >= 1 jumped by d_polys slot c - 1, degree d_deg[c - 1]), and the state
+// (bytes, a multiple of 16) copied to the C - 1 slots of d_copies, `stride`
+// bytes apart, for chunks 0 .. C-2 (the last chunk runs on d_state).
+hipError_t launch_split_setup(const uint8_t* d_state, uint8_t* d_copies, uint32_t bytes, uint64_t stride, uint32_t C,
+                              uint8_t* d_out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* d_polys,
+                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, hipStream_t stream);
+
 // Jump `count` copies of one state, each by its own polynomial (the chunks of
 // a split call), then fix their positions. d_src holds the window all copies
 // start from and is not one of them. d_parts as for launch_jump.
@@ -116,10 +125,6 @@ hipError_t noalloc_scratch(int device, BatchTask** d_tasks, uint32_t** d_counter
 
 // Copy states: task i copies tasks[i].src to tasks[i].dst (bytes, a multiple of 16).
 hipError_t launch_copy_states(const CopyTask* d_tasks, uint32_t count, uint32_t bytes, hipStream_t stream);
-
-// Copy the state at src (bytes, a multiple of 16) to count slots dst + i*stride.
-hipError_t launch_replicate(const uint8_t* src, uint8_t* dst, uint32_t bytes, uint64_t stride, uint32_t count,
-                            hipStream_t stream);
 
 // Whether the combination is compiled in; threads and occupancy of a shape.
 bool generate_supported(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind);
