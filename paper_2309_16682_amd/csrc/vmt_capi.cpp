@@ -439,7 +439,8 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t off_bt = (C - 1) * sbs;
     const size_t off_jt = off_bt + (C * sizeof(vmt::BatchTask) + 255) / 256 * 256;
     const size_t off_ctr = off_jt + ((C - 1) * sizeof(vmt::JumpTask) + 255) / 256 * 256;
-    const size_t off_parts = off_ctr + 256;
+    const size_t off_done = off_ctr + 256;  // one counter per chunk for the lane-group generation
+    const size_t off_parts = off_done + (C * sizeof(uint32_t) + 255) / 256 * 256;
     const size_t parts_bytes = vmt::split_jump_parts_bytes(info.variant, M, C - 1);
     const size_t total = off_parts + parts_bytes;
     uint8_t* buf = nullptr;
@@ -448,9 +449,10 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
     auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
+    auto* d_done = reinterpret_cast<uint32_t*>(buf + off_done);
     // copies for chunks 0 .. C-2, the state itself for the last; the task lists are written on the device
     e = vmt::launch_split_setup(d_state, buf, (uint32_t)sb, sbs, (uint32_t)C, d_out, E, n, (uint32_t)eb, polys, d_deg,
-                                d_bt, d_jt, stream);
+                                d_bt, d_jt, d_done, stream);
     // copy 0 is chunk 0: it is not jumped and holds the window every other chunk starts from
     const vmt::JumpTask jt0{C > 2 ? buf + sbs : d_state, polys, 0u, deg0, nullptr};  // the first jump task, as written
     if (e == hipSuccess)
@@ -460,7 +462,7 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
         if (vmt::is_sfmt(info.variant)) {
             e = vmt::launch_batch_sfmt(info.variant, M, M < 16 ? M : 16, out_kind, d_bt, (uint32_t)C, stream);
         } else if (lpw < M) {  // each chunk's lanes spread over M / lpw workgroups
-            e = vmt::launch_batch_gen_mt(info.variant, M, lpw, out_kind, d_bt, (uint32_t)C, stream);
+            e = vmt::launch_batch_gen_mt(info.variant, M, lpw, out_kind, d_bt, (uint32_t)C, stream, d_done);
         } else {
             vmt::BatchShape shape;
             vmt::ctx_batch_shape(ctx, info.variant, M, out_kind, &shape);

@@ -897,19 +897,41 @@ __global__ __launch_bounds__(64 * kSfmtWavesPerWg, 3) void batch_sfmt_kernel(con
     G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, g, groups == 1);
 }
 
+// Position of a task's state after its len elements (from the position before).
+__device__ __forceinline__ void batch_final_pos(const BatchTask& task) {
+    StateHeader* hdr = reinterpret_cast<StateHeader*>(task.state);
+    const uint64_t B = hdr->block, pos = hdr->pos, len = task.len;
+    const uint64_t head = len < B - pos ? len : B - pos;
+    const uint64_t rest = len - head;
+    const uint64_t nblocks = (rest + B - 1) / B;
+    hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * B) : (uint32_t)(pos + head);
+}
+
 // Batched MT generation by lane groups (the chunks of a split call):
 // workgroup (g, t) runs lane group g of task t with the single-state code, so
 // a chunk's M lanes spread over M / LPW workgroups. With several groups per
-// state the positions are fixed afterwards (finalize_batch_pos).
+// state the positions are fixed afterwards: by finalize_batch_pos, or, with
+// `done` (one zeroed counter per task), by the last of a task's workgroups to
+// finish. That one counts after every other has, and each counts after its
+// own reads of the position have returned (the barrier), so no read of the old
+// position follows the write, which depends on the count. The count is
+// relaxed: a release would write back the L2's dirty output lines at every
+// workgroup's end; the kernel's end publishes the position.
 template <class P, int LPW, int OUT>
 __global__ __launch_bounds__((mt_threads<P, LPW>())) void batch_gen_mt_kernel(const BatchTask* tasks, uint32_t count,
-                                                                           uint32_t groups) {
+                                                                           uint32_t groups, uint32_t* done) {
     using G = MtGen<P, LPW, mt_threads<P, LPW>(), OUT>;
     __shared__ __attribute__((aligned(16))) typename P::W win[(P::N + 1) * LPW];
     const GroupSlot gs = group_slot(blockIdx.x, groups, 0);
     if (gs.state >= count) return;
     const BatchTask task = tasks[gs.state];
     G::run(task.state, reinterpret_cast<typename G::OutT*>(task.out), task.len, gs.group, groups == 1, win);
+    if (done && groups > 1) {
+        __syncthreads();  // the whole workgroup is past its reads of the header
+        if (threadIdx.x == 0 &&
+            __hip_atomic_fetch_add(done + gs.state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == groups - 1)
+            batch_final_pos(task);
+    }
 }
 
 // Copy whole states (header and window; `bytes` a multiple of 16): task y
@@ -927,15 +949,17 @@ __global__ void copy_states(const CopyTask* tasks, uint32_t bytes) {
 // [c E, (c + 1) E), the last one the rest of n, and runs on copy c (the last
 // chunk on the state itself); chunk c >= 1 is jumped by slot c - 1 of `polys`
 // (degree deg[c - 1]). Workgroup (x, c) copies its share of copy c, and
-// thread 0 of workgroup (0, c) writes chunk c's tasks.
+// thread 0 of workgroup (0, c) writes chunk c's tasks and zeroes its counter
+// in `done` (if given) for the generation's workgroups.
 __global__ void split_setup(const uint8_t* state, uint8_t* copies, uint32_t bytes, uint64_t stride, uint32_t C,
                             uint8_t* out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* polys,
-                            const uint32_t* deg, BatchTask* bt, JumpTask* jt) {
+                            const uint32_t* deg, BatchTask* bt, JumpTask* jt, uint32_t* done) {
     const uint32_t c = blockIdx.y;
     uint8_t* st = c + 1 == C ? const_cast<uint8_t*>(state) : copies + stride * c;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bt[c] = BatchTask{st, out + (uint64_t)c * E * eb, c + 1 < C ? E : n - (uint64_t)c * E, nullptr};
         if (c) jt[c - 1] = JumpTask{st, polys + (size_t)(c - 1) * kPolyWords, 0u, deg[c - 1], nullptr};
+        if (done) done[c] = 0;
     }
     if (c + 1 == C) return;
     const uint4* s = reinterpret_cast<const uint4*>(state);
@@ -959,13 +983,7 @@ __global__ void reset_counter(uint32_t* c) { c[threadIdx.x] = 0; }
 __global__ void finalize_batch_pos(const BatchTask* tasks, uint32_t count) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const BatchTask task = tasks[i];
-    StateHeader* hdr = reinterpret_cast<StateHeader*>(task.state);
-    const uint64_t B = hdr->block, pos = hdr->pos, len = task.len;
-    const uint64_t head = len < B - pos ? len : B - pos;
-    const uint64_t rest = len - head;
-    const uint64_t nblocks = (rest + B - 1) / B;
-    hdr->pos = nblocks ? (uint32_t)(rest - (nblocks - 1) * B) : (uint32_t)(pos + head);
+    batch_final_pos(tasks[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2275,38 +2293,39 @@ hipError_t launch_batch_sfmt(uint32_t variant, uint32_t M, uint32_t lpw, int out
 }
 
 hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
-                               uint32_t count, hipStream_t stream) {
+                               uint32_t count, hipStream_t stream, uint32_t* d_done) {
     if (count == 0) return hipSuccess;
     const uint32_t groups = M / lpw;
     const dim3 grid(group_grid(count, groups));
     if (variant == kMT32) {
         if (out_kind == kOutU32) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 0><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups, d_done))
         } else {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT32P, LL, 1><<<grid, mt_threads<MT32P, LL>(), 0, stream>>>(d_tasks, count, groups, d_done))
         }
     } else {
         if (out_kind == kOutU64) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 0><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups, d_done))
         } else if (out_kind == kOutF64) {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 2><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups, d_done))
         } else {
-            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups))
+            VMT_LPW_SWITCH(lpw, batch_gen_mt_kernel<MT64P, LL, 1><<<grid, mt_threads<MT64P, LL>(), 0, stream>>>(d_tasks, count, groups, d_done))
         }
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || lpw == M) return e;
+    if (e != hipSuccess || lpw == M || d_done) return e;
     finalize_batch_pos<<<(count + 255) / 256, 256, 0, stream>>>(d_tasks, count);
     return hipGetLastError();
 }
 
 hipError_t launch_split_setup(const uint8_t* d_state, uint8_t* d_copies, uint32_t bytes, uint64_t stride, uint32_t C,
                               uint8_t* d_out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* d_polys,
-                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, hipStream_t stream) {
+                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, uint32_t* d_done,
+                              hipStream_t stream) {
     if (C == 0) return hipSuccess;
     const uint32_t per = (bytes / 16 + 255) / 256;
     split_setup<<<dim3(per < 64 ? per : 64, C), 256, 0, stream>>>(d_state, d_copies, bytes, stride, C, d_out, E, n, eb,
-                                                                  d_polys, d_deg, d_bt, d_jt);
+                                                                  d_polys, d_deg, d_bt, d_jt, d_done);
     return hipGetLastError();
 }
 

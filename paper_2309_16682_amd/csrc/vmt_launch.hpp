@@ -45,10 +45,12 @@ size_t split_jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count);  //
 // eb bytes into d_out; generation tasks d_bt[C], jump tasks d_jt[C-1] (chunk
 // c >= 1 jumped by d_polys slot c - 1, degree d_deg[c - 1]), and the state
 // (bytes, a multiple of 16) copied to the C - 1 slots of d_copies, `stride`
-// bytes apart, for chunks 0 .. C-2 (the last chunk runs on d_state).
+// bytes apart, for chunks 0 .. C-2 (the last chunk runs on d_state); d_done
+// (C counters, or nullptr) is zeroed for launch_batch_gen_mt.
 hipError_t launch_split_setup(const uint8_t* d_state, uint8_t* d_copies, uint32_t bytes, uint64_t stride, uint32_t C,
                               uint8_t* d_out, uint64_t E, uint64_t n, uint32_t eb, const uint64_t* d_polys,
-                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, hipStream_t stream);
+                              const uint32_t* d_deg, BatchTask* d_bt, JumpTask* d_jt, uint32_t* d_done,
+                              hipStream_t stream);
 
 // Jump `count` copies of one state, each by its own polynomial (the chunks of
 // a split call), then fix their positions. d_src holds the window all copies
@@ -94,9 +96,11 @@ hipError_t launch_batch(uint32_t variant, uint32_t M, int out_kind, const BatchS
 
 // MT19937-32/-64 tasks by lane groups: M / lpw workgroups per task, each
 // running lpw lanes (lpw a power of two dividing M, at most 16); positions
-// are maintained like launch_generate's.
+// are maintained like launch_generate's. With lpw < M the positions are fixed
+// by a second launch, or, given d_done (count counters, zeroed), by the last
+// workgroup of each task.
 hipError_t launch_batch_gen_mt(uint32_t variant, uint32_t M, uint32_t lpw, int out_kind, const BatchTask* d_tasks,
-                               uint32_t count, hipStream_t stream);
+                               uint32_t count, hipStream_t stream, uint32_t* d_done = nullptr);
 
 // Batched SFMT generation (one lane group of lpw lanes per workgroup, tasks
 // of one M); positions are maintained like launch_generate's.
