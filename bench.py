@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "cd49b42695187f1d22923cbaf0a351928ce409af0e82856f8b5f95b1e41b154c",
+    "kernel_fingerprint": "95ea2a461681d06957b3764273d752359ad7f1a5c79e6f821540372c76f6e49b",
     "shapes": {
-        (512, 16, 2): (878015616, 96283548000),
-        (512, 8, 2): (878085760, 96283547808),
-        (256, 16, 2): (878127872, 96283547829),
-        (256, 8, 3): (878318891, 96283564256),
-        (960, 16, 2): (878177280, 96283548821),
+        (512, 16, 2): (877900160, 96283548011),
+        (512, 8, 2): (878114048, 96283547872),
+        (256, 16, 2): (878155947, 96283547829),
+        (256, 8, 3): (878342357, 96283564331),
+        (960, 16, 2): (878033749, 96283549045),
     },
 }
 
