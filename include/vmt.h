@@ -24,11 +24,15 @@
  *     VMT_EVARIANT, VMT_ESTATE) has enqueued nothing and left the state
  *     unchanged. After VMT_EDEVICE or VMT_ENOMEM from the HIP runtime part of
  *     the call's work may have been enqueued: the state is then undefined.
- *   - Allocation: batched calls, split generation and jumps allocate their
- *     task lists (and split generation its scratch copies of the state)
- *     stream-ordered (hipMallocAsync on the call's stream); plans and servers
- *     allocate once, at creation. vmt_batch_generate_noalloc allocates
- *     nothing (its task list goes into a fixed device scratch array).
+ *   - Allocation: batched calls and jumps allocate their task lists (and
+ *     jumps of few MT lanes their partial sums) stream-ordered (hipMallocAsync
+ *     on the call's stream). Split generation uses a workspace per stream
+ *     owned by the context (copies of the state, task lists, partial sums),
+ *     grown stream-ordered when a call needs more and kept until
+ *     vmt_ctx_destroy; under stream capture it allocates its own,
+ *     stream-ordered. Plans and servers allocate once, at creation.
+ *     vmt_batch_generate_noalloc allocates nothing (its task list goes into a
+ *     fixed device scratch array).
  *   - Concurrency: calls on different states may overlap on different
  *     streams. Calls on one state must be ordered by the caller (one stream).
  *
@@ -448,7 +452,7 @@ int vmt_check_stream(vmt_ctx* ctx, int variant, uint32_t M, int out_kind, const 
  * workgroups per chunk) when lanes_per_wg is below M; SFMT chunks run
  * min(M, 16) lanes per workgroup. Splitting needs the jump tables of the
  * chunk offsets (computed on the host once per chunk length) and a scratch
- * copy of the state per chunk (stream-ordered allocation). */
+ * copy of the state per chunk (in the context's workspace for the stream). */
 enum { VMT_FAMILY_GENERATE = 0, VMT_FAMILY_BATCH = 1 };
 
 typedef struct {

@@ -97,6 +97,10 @@ struct vmt_ctx {
     std::map<uint32_t, SplitTable> split[vmt::kVariants];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
     std::map<uint32_t, CheckPoly> check[vmt::kVariants];   // M -> recurrence polynomial of the V-stream's bits
     std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
+    // Workspace of split calls per stream (copies, task lists, counters, jump parts): calls on one stream use it
+    // in stream order, and everything in it is written by the call's own launches, so it is reused from call to
+    // call without a stream-ordered allocation and free each time (those leave the GPU idle between calls).
+    std::unordered_map<hipStream_t, std::pair<uint8_t*, size_t>> split_ws;
 };
 
 struct vmt_batch_plan {
@@ -443,9 +447,29 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t off_parts = off_done + (C * sizeof(uint32_t) + 255) / 256 * 256;
     const size_t parts_bytes = vmt::split_jump_parts_bytes(info.variant, M, C - 1);
     const size_t total = off_parts + parts_bytes;
+    // the stream's workspace, grown when too small (the old one freed behind the work queued on the stream);
+    // under stream capture a stream-ordered allocation of the call's own, so that a graph owns its memory
+    hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &capturing);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    const bool own = capturing != hipStreamCaptureStatusNone;
     uint8_t* buf = nullptr;
-    hipError_t e = hipMallocAsync((void**)&buf, total, stream);
-    if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
+    if (own) {
+        e = hipMallocAsync((void**)&buf, total, stream);
+        if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
+    } else {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto& ws = ctx->split_ws[stream];
+        if (ws.second < total) {
+            const size_t cap = std::max(total, 2 * ws.second);
+            uint8_t* p = nullptr;
+            e = hipMallocAsync((void**)&p, cap, stream);
+            if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split workspace): %s", hipGetErrorString(e));
+            if (ws.first) (void)hipFreeAsync(ws.first, stream);
+            ws = {p, cap};
+        }
+        buf = ws.first;
+    }
     auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
     auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
@@ -471,7 +495,7 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
                 e = vmt::launch_batch(info.variant, M, out_kind, shape, d_bt, (uint32_t)C, d_ctr, stream);
         }
     }
-    (void)hipFreeAsync(buf, stream);
+    if (own) (void)hipFreeAsync(buf, stream);
     if (e != hipSuccess) return hip_fail(e, "split generate");
     return VMT_OK;
 }
@@ -739,6 +763,9 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
             for (auto& kv : ctx->check[v]) (void)hipFree(kv.second.d);
         }
         for (void* p : ctx->retired) (void)hipFree(p);
+        // stream-ordered allocations: freed on the null stream (their own streams may be gone), then waited for
+        for (auto& kv : ctx->split_ws) (void)hipFreeAsync(kv.second.first, nullptr);
+        (void)hipDeviceSynchronize();
     }
     delete ctx;
     return VMT_OK;

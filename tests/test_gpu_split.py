@@ -158,3 +158,30 @@ def test_split_setting_is_validated(ctx):
     assert vmt.vmt_shape_get(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32).split_log2 == 255
     vmt.vmt_shape_set(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32)
     assert vmt.vmt_shape_get(ctx, GEN, MT32, 16, vmt.VMT_OUT_U32).split_log2 == 0
+
+
+def test_split_calls_on_two_streams_with_growing_workspaces(ctx):
+    # each stream has its own workspace in the context, grown as calls get larger; two states split side by side
+    # on two streams must each equal their oracle stream
+    M = 16
+    n_small, n_large = 3 * (1 << 16) * M + 77, 9 * (1 << 16) * M + 5
+    say(f"case split on two streams n={n_small},{n_large}")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sts, refs = [], []
+    for seed in (31, 32):
+        st = vmt.new_state(MT32, M)
+        vmt.vmt_init_genrand(ctx, MT32, seed, M, st)
+        sts.append(st)
+        refs.append(oracle_stream(MT32, M, seed=seed))
+    torch.cuda.synchronize()
+    vmt.vmt_shape_set(ctx, GEN, MT32, M, vmt.VMT_OUT_U32, lanes_per_wg=1, split_log2=16)
+    try:
+        for n in (n_small, n_large, n_small):
+            outs = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in streams]
+            for st, out, s in zip(sts, outs, streams):
+                vmt.vmt_generate_u32(ctx, st, n, out, stream=s.cuda_stream)
+            torch.cuda.synchronize()
+            for out, ref in zip(outs, refs):
+                np.testing.assert_array_equal(as_u(out.cpu(), MT32), ref.generate(n))
+    finally:
+        vmt.vmt_shape_set(ctx, GEN, MT32, M, vmt.VMT_OUT_U32)
