@@ -24,13 +24,13 @@
  *     VMT_EVARIANT, VMT_ESTATE) has enqueued nothing and left the state
  *     unchanged. After VMT_EDEVICE or VMT_ENOMEM from the HIP runtime part of
  *     the call's work may have been enqueued: the state is then undefined.
- *   - Allocation: batched calls and jumps allocate their task lists (and
- *     jumps of few MT lanes their partial sums) stream-ordered (hipMallocAsync
- *     on the call's stream). Split generation uses a workspace per stream
- *     owned by the context (copies of the state, task lists, partial sums),
- *     grown stream-ordered when a call needs more and kept until
- *     vmt_ctx_destroy; under stream capture it allocates its own,
- *     stream-ordered. Plans and servers allocate once, at creation.
+ *   - Allocation: batched calls and batched jumps allocate their task lists
+ *     stream-ordered (hipMallocAsync on the call's stream). Split generation
+ *     and jumps of few MT lanes use a workspace per stream owned by the
+ *     context (copies of the state, task lists, partial sums), grown
+ *     stream-ordered when a call needs more and kept until vmt_ctx_destroy;
+ *     under stream capture they allocate their own, stream-ordered. Plans and
+ *     servers allocate once, at creation.
  *     vmt_batch_generate_noalloc allocates nothing (its task list goes into a
  *     fixed device scratch array).
  *   - Concurrency: calls on different states may overlap on different

@@ -97,9 +97,10 @@ struct vmt_ctx {
     std::map<uint32_t, SplitTable> split[vmt::kVariants];  // log2 chunk -> t^(c 2^v) mod mu, c = 1, 2, ...
     std::map<uint32_t, CheckPoly> check[vmt::kVariants];   // M -> recurrence polynomial of the V-stream's bits
     std::vector<void*> retired;                 // replaced device tables (queued kernels may still read them)
-    // Workspace of split calls per stream (copies, task lists, counters, jump parts): calls on one stream use it
-    // in stream order, and everything in it is written by the call's own launches, so it is reused from call to
-    // call without a stream-ordered allocation and free each time (those leave the GPU idle between calls).
+    // Workspace per stream of split calls and jumps (copies, task lists, counters, jump parts): calls on one stream
+    // use it in stream order, and everything in it that a call reads is written by the call's own launches, so it
+    // is reused from call to call without a stream-ordered allocation and free each time (those leave the GPU idle
+    // between calls).
     std::unordered_map<hipStream_t, std::pair<uint8_t*, size_t>> split_ws;
 };
 
@@ -419,6 +420,33 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
     return VMT_OK;
 }
 
+// Device scratch of `bytes` for one call on `stream`: the context's workspace
+// for the stream (grown stream-ordered when too small, the old one freed
+// behind the work queued on the stream), or, under stream capture, a
+// stream-ordered allocation of the call's own (*own = true; the caller frees
+// it stream-ordered), so that a graph owns its memory. Calls on one stream use
+// the workspace in stream order; each must write every byte of it that it
+// reads.
+hipError_t stream_workspace(vmt_ctx* ctx, hipStream_t stream, size_t bytes, uint8_t** buf, bool* own) {
+    hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &capturing);
+    if (e != hipSuccess) return e;
+    *own = capturing != hipStreamCaptureStatusNone;
+    if (*own) return hipMallocAsync((void**)buf, bytes, stream);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto& ws = ctx->split_ws[stream];
+    if (ws.second < bytes) {
+        const size_t cap = std::max(bytes, 2 * ws.second);
+        uint8_t* p = nullptr;
+        e = hipMallocAsync((void**)&p, cap, stream);
+        if (e != hipSuccess) return e;
+        if (ws.first) (void)hipFreeAsync(ws.first, stream);
+        ws = {p, cap};
+    }
+    *buf = ws.first;
+    return hipSuccess;
+}
+
 int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64_t n, uint8_t* d_out, int out_kind,
                    int v, uint32_t lpw, hipStream_t stream) {
     const uint32_t M = info.M;
@@ -447,29 +475,10 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t off_parts = off_done + (C * sizeof(uint32_t) + 255) / 256 * 256;
     const size_t parts_bytes = vmt::split_jump_parts_bytes(info.variant, M, C - 1);
     const size_t total = off_parts + parts_bytes;
-    // the stream's workspace, grown when too small (the old one freed behind the work queued on the stream);
-    // under stream capture a stream-ordered allocation of the call's own, so that a graph owns its memory
-    hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(stream, &capturing);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
-    const bool own = capturing != hipStreamCaptureStatusNone;
     uint8_t* buf = nullptr;
-    if (own) {
-        e = hipMallocAsync((void**)&buf, total, stream);
-        if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split): %s", hipGetErrorString(e));
-    } else {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto& ws = ctx->split_ws[stream];
-        if (ws.second < total) {
-            const size_t cap = std::max(total, 2 * ws.second);
-            uint8_t* p = nullptr;
-            e = hipMallocAsync((void**)&p, cap, stream);
-            if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(split workspace): %s", hipGetErrorString(e));
-            if (ws.first) (void)hipFreeAsync(ws.first, stream);
-            ws = {p, cap};
-        }
-        buf = ws.first;
-    }
+    bool own = false;
+    hipError_t e = stream_workspace(ctx, stream, total, &buf, &own);
+    if (e != hipSuccess) return fail(VMT_ENOMEM, "split workspace: %s", hipGetErrorString(e));
     auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
     auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
@@ -547,16 +556,19 @@ int init_common(vmt_ctx* ctx, int variant, uint32_t M, void* d_state, const vmt:
 
 // A jump launch with, where it applies, the scratch for lane sums split over
 // several workgroups (stream-ordered, freed behind the launches).
-hipError_t jump_launch(uint32_t variant, uint32_t M, const vmt::JumpTask* d_tasks, const vmt::JumpTask& one,
-                       uint32_t count, hipStream_t stream) {
+// A jump launch with, where it applies, scratch for lane sums split over
+// several workgroups (the stream's workspace).
+hipError_t jump_launch(vmt_ctx* ctx, uint32_t variant, uint32_t M, const vmt::JumpTask* d_tasks,
+                       const vmt::JumpTask& one, uint32_t count, hipStream_t stream) {
     const size_t pb = vmt::jump_parts_bytes(variant, M, count);
-    void* d_parts = nullptr;
+    uint8_t* d_parts = nullptr;
+    bool own = false;
     if (pb) {
-        hipError_t e = hipMallocAsync(&d_parts, pb, stream);
+        hipError_t e = stream_workspace(ctx, stream, pb, &d_parts, &own);
         if (e != hipSuccess) return e;
     }
     hipError_t e = vmt::launch_jump(variant, M, d_tasks, one, count, stream, d_parts);
-    if (d_parts) (void)hipFreeAsync(d_parts, stream);
+    if (own) (void)hipFreeAsync(d_parts, stream);
     return e;
 }
 
@@ -573,7 +585,7 @@ int jump_with(vmt_ctx* ctx, void* d_state, const std::vector<uint64_t>& dist, co
         if (st) return st;
     }
     vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
-    hipError_t e = jump_launch(info.variant, info.M, nullptr, task, 1, stream);
+    hipError_t e = jump_launch(ctx, info.variant, info.M, nullptr, task, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "jump launch");
     return VMT_OK;
 }
@@ -912,7 +924,7 @@ int vmt_jump_pow2(vmt_ctx* ctx, void* d_state, uint32_t k, hipStream_t stream) {
         if (st) return st;
     }
     vmt::JumpTask task{static_cast<uint8_t*>(d_state), dp->d, 0u, dp->deg, nullptr};
-    hipError_t e = jump_launch(info.variant, info.M, nullptr, task, 1, stream);
+    hipError_t e = jump_launch(ctx, info.variant, info.M, nullptr, task, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "jump launch");
     return VMT_OK;
 }
@@ -942,7 +954,7 @@ int vmt_jump_pow2_batch(vmt_ctx* ctx, void* const* d_states, const uint32_t* ks,
     hipError_t e = hipMallocAsync((void**)&d_tasks, count * sizeof(vmt::JumpTask), stream);
     if (e != hipSuccess) return fail(VMT_ENOMEM, "hipMallocAsync(jump tasks): %s", hipGetErrorString(e));
     e = hipMemcpyAsync(d_tasks, tasks.data(), count * sizeof(vmt::JumpTask), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = jump_launch(info.variant, info.M, d_tasks, tasks[0], (uint32_t)count, stream);
+    if (e == hipSuccess) e = jump_launch(ctx, info.variant, info.M, d_tasks, tasks[0], (uint32_t)count, stream);
     (void)hipFreeAsync(d_tasks, stream);
     if (e != hipSuccess) return hip_fail(e, "jump batch");
     return VMT_OK;
