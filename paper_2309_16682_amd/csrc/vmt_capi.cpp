@@ -83,6 +83,15 @@ struct CheckPoly {
 
 }  // namespace
 
+// A stream's workspace (see vmt_ctx::split_ws); `mu` is held from taking the
+// workspace until the call's last launch is enqueued, so that calls issued on
+// one stream from several host threads do not interleave their launches over it.
+struct StreamWorkspace {
+    uint8_t* buf = nullptr;
+    size_t cap = 0;
+    std::mutex mu;
+};
+
 struct vmt_ctx {
     int device = -1;
     std::mutex mu;
@@ -101,7 +110,7 @@ struct vmt_ctx {
     // use it in stream order, and everything in it that a call reads is written by the call's own launches, so it
     // is reused from call to call without a stream-ordered allocation and free each time (those leave the GPU idle
     // between calls).
-    std::unordered_map<hipStream_t, std::pair<uint8_t*, size_t>> split_ws;
+    std::unordered_map<hipStream_t, std::unique_ptr<StreamWorkspace>> split_ws;
 };
 
 struct vmt_batch_plan {
@@ -422,28 +431,37 @@ int split_table(vmt_ctx* ctx, int variant, int v, size_t need, SplitTable** out)
 
 // Device scratch of `bytes` for one call on `stream`: the context's workspace
 // for the stream (grown stream-ordered when too small, the old one freed
-// behind the work queued on the stream), or, under stream capture, a
-// stream-ordered allocation of the call's own (*own = true; the caller frees
-// it stream-ordered), so that a graph owns its memory. Calls on one stream use
-// the workspace in stream order; each must write every byte of it that it
-// reads.
-hipError_t stream_workspace(vmt_ctx* ctx, hipStream_t stream, size_t bytes, uint8_t** buf, bool* own) {
+// behind the work queued on the stream), with the stream's lock taken into
+// `lock` (hold it until the call's launches are enqueued), or, under stream
+// capture, a stream-ordered allocation of the call's own (*own = true; the
+// caller frees it stream-ordered), so that a graph owns its memory. Calls on
+// one stream use the workspace in stream order; each must write every byte of
+// it that it reads.
+hipError_t stream_workspace(vmt_ctx* ctx, hipStream_t stream, size_t bytes, uint8_t** buf, bool* own,
+                            std::unique_lock<std::mutex>* lock) {
     hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(stream, &capturing);
     if (e != hipSuccess) return e;
     *own = capturing != hipStreamCaptureStatusNone;
     if (*own) return hipMallocAsync((void**)buf, bytes, stream);
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    auto& ws = ctx->split_ws[stream];
-    if (ws.second < bytes) {
-        const size_t cap = std::max(bytes, 2 * ws.second);
+    StreamWorkspace* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto& slot = ctx->split_ws[stream];
+        if (!slot) slot = std::make_unique<StreamWorkspace>();
+        ws = slot.get();
+    }
+    *lock = std::unique_lock<std::mutex>(ws->mu);
+    if (ws->cap < bytes) {
+        const size_t cap = std::max(bytes, 2 * ws->cap);
         uint8_t* p = nullptr;
         e = hipMallocAsync((void**)&p, cap, stream);
         if (e != hipSuccess) return e;
-        if (ws.first) (void)hipFreeAsync(ws.first, stream);
-        ws = {p, cap};
+        if (ws->buf) (void)hipFreeAsync(ws->buf, stream);
+        ws->buf = p;
+        ws->cap = cap;
     }
-    *buf = ws.first;
+    *buf = ws->buf;
     return hipSuccess;
 }
 
@@ -477,8 +495,11 @@ int generate_split(vmt_ctx* ctx, const StateInfo& info, uint8_t* d_state, uint64
     const size_t total = off_parts + parts_bytes;
     uint8_t* buf = nullptr;
     bool own = false;
-    hipError_t e = stream_workspace(ctx, stream, total, &buf, &own);
-    if (e != hipSuccess) return fail(VMT_ENOMEM, "split workspace: %s", hipGetErrorString(e));
+    std::unique_lock<std::mutex> ws_lock;
+    hipError_t e = stream_workspace(ctx, stream, total, &buf, &own, &ws_lock);
+    if (e != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(VMT_ENOMEM, "split workspace: %s", hipGetErrorString(e))
+                                        : hip_fail(e, "split workspace");
     auto* d_bt = reinterpret_cast<vmt::BatchTask*>(buf + off_bt);
     auto* d_jt = reinterpret_cast<vmt::JumpTask*>(buf + off_jt);
     auto* d_ctr = reinterpret_cast<uint32_t*>(buf + off_ctr);
@@ -563,8 +584,9 @@ hipError_t jump_launch(vmt_ctx* ctx, uint32_t variant, uint32_t M, const vmt::Ju
     const size_t pb = vmt::jump_parts_bytes(variant, M, count);
     uint8_t* d_parts = nullptr;
     bool own = false;
+    std::unique_lock<std::mutex> ws_lock;
     if (pb) {
-        hipError_t e = stream_workspace(ctx, stream, pb, &d_parts, &own);
+        hipError_t e = stream_workspace(ctx, stream, pb, &d_parts, &own, &ws_lock);
         if (e != hipSuccess) return e;
     }
     hipError_t e = vmt::launch_jump(variant, M, d_tasks, one, count, stream, d_parts);
@@ -776,7 +798,7 @@ int vmt_ctx_destroy(vmt_ctx* ctx) {
         }
         for (void* p : ctx->retired) (void)hipFree(p);
         // stream-ordered allocations: freed on the null stream (their own streams may be gone), then waited for
-        for (auto& kv : ctx->split_ws) (void)hipFreeAsync(kv.second.first, nullptr);
+        for (auto& kv : ctx->split_ws) (void)hipFreeAsync(kv.second->buf, nullptr);
         (void)hipDeviceSynchronize();
     }
     delete ctx;
