@@ -185,3 +185,45 @@ def test_split_calls_on_two_streams_with_growing_workspaces(ctx):
                 np.testing.assert_array_equal(as_u(out.cpu(), MT32), ref.generate(n))
     finally:
         vmt.vmt_shape_set(ctx, GEN, MT32, M, vmt.VMT_OUT_U32)
+
+
+def test_split_calls_from_two_host_threads_on_one_stream(ctx):
+    # two host threads issue split calls for their own states on one stream: the stream's workspace serves both,
+    # one call at a time, and each state's outputs equal its oracle stream call after call
+    import threading
+
+    M, calls = 16, 4
+    n = 3 * (1 << 16) * M + 7
+    say(f"case split from two threads n={n} calls={calls}")
+    stream = torch.cuda.Stream()
+    sts, outs = [], []
+    for seed in (41, 42):
+        st = vmt.new_state(MT32, M)
+        vmt.vmt_init_genrand(ctx, MT32, seed, M, st)
+        sts.append(st)
+        outs.append([torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(calls)])
+    torch.cuda.synchronize()
+    vmt.vmt_shape_set(ctx, GEN, MT32, M, vmt.VMT_OUT_U32, lanes_per_wg=1, split_log2=16)
+    errors = []
+
+    def work(i):
+        try:
+            for out in outs[i]:
+                vmt.vmt_generate_u32(ctx, sts[i], n, out, stream=stream.cuda_stream)
+        except Exception as exc:  # reported by the main thread
+            errors.append(exc)
+
+    try:
+        threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+    finally:
+        vmt.vmt_shape_set(ctx, GEN, MT32, M, vmt.VMT_OUT_U32)
+    assert not errors, errors
+    for i, seed in enumerate((41, 42)):
+        ref = oracle_stream(MT32, M, seed=seed)
+        for out in outs[i]:
+            np.testing.assert_array_equal(as_u(out.cpu(), MT32), ref.generate(n))
