@@ -399,3 +399,35 @@ def test_M1_stream_is_the_standard_library_engine(ctx, variant, bits):
             np.testing.assert_array_equal(gen(ctx, st, variant, n), ref, err_msg=f"split {split}")
         finally:
             vmt.vmt_shape_set(ctx, vmt.VMT_FAMILY_GENERATE, variant, 1, native)
+
+
+@pytest.mark.parametrize("variant,M", [(MT32, 16), (MT64, 8)])
+def test_jump_captured_in_a_graph(ctx, variant, M):
+    # under stream capture a jump of few MT lanes takes a stream-ordered allocation of its own for its partial sums
+    # (the graph owns it) instead of the stream's workspace; every replay must jump the state like an eager call
+    k = 100
+    say(f"case jump in a graph variant={variant} M={M}")
+    st, ref = vmt.new_state(variant, M), vmt.new_state(variant, M)
+    for s in (st, ref):
+        vmt.vmt_init_genrand(ctx, variant, 5489, M, s)
+        vmt.vmt_jump_pow2(ctx, s, k)  # builds the polynomial tables outside the capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            vmt.vmt_jump_pow2(ctx, st, k)
+    for rep in range(3):
+        g.replay()
+        vmt.vmt_jump_pow2(ctx, ref, k)  # eager, on the default stream
+        torch.cuda.synchronize()
+        assert torch.equal(st, ref), f"replay {rep}"
+    # and the state generates the oracle's stream jumped by 2^k four times (once before the capture, three replays)
+    n = 3 * BLOCK[variant] * M + 11
+    out = torch.zeros(n, dtype=torch.int64 if variant == MT64 else torch.int32, device="cuda")
+    (vmt.vmt_generate_u64 if variant == MT64 else vmt.vmt_generate_u32)(ctx, st, n, out)
+    torch.cuda.synchronize()
+    r = oracle_stream(variant, M, seed=5489)
+    for _ in range(4):
+        r.jump(pow2_poly(variant, k))
+    np.testing.assert_array_equal(as_u(out.cpu(), variant), r.generate(n))
