@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "95ea2a461681d06957b3764273d752359ad7f1a5c79e6f821540372c76f6e49b",
+    "kernel_fingerprint": "b4024990fe310c395af11a09c0165d46e7eb0c21c998316f00fe942773bfcb52",
     "shapes": {
-        (512, 16, 2): (877900160, 96283548011),
-        (512, 8, 2): (878114048, 96283547872),
-        (256, 16, 2): (878155947, 96283547829),
-        (256, 8, 3): (878342357, 96283564331),
-        (960, 16, 2): (878033749, 96283549045),
+        (512, 16, 2): (877911467, 96283547915),
+        (512, 8, 2): (878132523, 96283547808),
+        (256, 16, 2): (878079573, 96283547797),
+        (256, 8, 3): (878295552, 96283564277),
+        (960, 16, 2): (877968939, 96283548960),
     },
 }
 

@@ -2030,6 +2030,7 @@ size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
 #ifndef VMT_SHARE_WGS
 #define VMT_SHARE_WGS 512
 #endif
+static_assert(VMT_JUMP_PARTS_MAX <= 32 && VMT_SHARE_PARTS_MAX <= 32, "launch_reduce_parts instantiates up to 32 parts");
 
 uint32_t split_share_parts(uint32_t variant, uint32_t M, uint64_t count) {
     // MT split jumps whose copies, 16 per workgroup, give each lane fewer than
