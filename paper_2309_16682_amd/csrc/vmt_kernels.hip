@@ -1142,6 +1142,86 @@ __device__ __forceinline__ void accumulate_block4(W (&acc)[(N + 63) / 64], const
     }
 }
 
+// Groups of five coefficients: as accumulate_block4, with the derived rows of
+// the 16 odd 5-bit patterns (derive_rows5). The coefficients are decoded 60 at
+// a time (12 groups, from two polynomial words), so no group straddles a
+// decoding step; the block's range [lo, hi) masks each pattern, so every term
+// taken lies in the block. Fewer window reads (one per nonzero group of 5)
+// for twice the derived rows.
+template <class W, int N>
+__device__ __forceinline__ void accumulate_block5(W (&acc)[(N + 63) / 64], const W* rows, int rstride,
+                                                  const uint64_t* poly, int k, int b, int max_deg, int lane, int clo,
+                                                  int chi) {
+    constexpr int S = (N + 63) / 64;
+    int lo = b * N - k, hi = (b + 1) * N - k;
+    if (lo < clo) lo = clo;
+    if (lo < 0) lo = 0;
+    if (hi > chi) hi = chi;
+    if (hi > max_deg + 1) hi = max_deg + 1;
+    if (lo >= hi) return;
+    const int off0 = k - b * N + lane;
+    const int u = lane < 12 ? lane : 0;
+    for (int base = lo / 60 * 60; base < hi; base += 60) {
+        const int w0 = base >> 6, sh = base & 63;
+        uint64_t bits = uniform(poly[w0]) >> sh;
+        if (sh > 4) bits |= uniform(poly[w0 + 1]) << (64 - sh);
+        bits &= (1ull << 60) - 1;
+        if (base < lo) bits &= ~0ull << (lo - base);
+        if (base + 60 > hi) bits &= (1ull << (hi - base)) - 1;
+        if (!bits) continue;
+        const uint32_t pat = (uint32_t)(bits >> (5 * u)) & 31u;
+        const int e0 = __builtin_ctz(pat | 32u);
+        const int grp_off = (int)((pat >> e0) >> 1) * rstride + 5 * u + e0;
+        uint64_t live = __ballot(lane < 12 && pat != 0) & 0xFFFull;
+        auto next_group = [&]() {
+            const int g = __builtin_ctzll(live);
+            live &= live - 1;
+            return base + __builtin_amdgcn_readlane(grp_off, g);
+        };
+        while (live) {
+            const W* sa = rows + off0 + next_group();
+            W va[S], vb[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) va[s] = sa[64 * s];
+            if (live) {
+                const W* sb = rows + off0 + next_group();
+#pragma unroll
+                for (int s = 0; s < S; ++s) vb[s] = sb[64 * s];
+#pragma unroll
+                for (int s = 0; s < S; ++s) acc[s] = xorw3(acc[s], va[s], vb[s]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s) acc[s] = xorw(acc[s], va[s]);
+            }
+        }
+    }
+}
+
+// Derived rows of the 16 odd 5-bit patterns q = 1, 3, .., 31 (row q >> 1;
+// row 0 is the raw row), for m in [0, 2N), words past the window counting as
+// zero: D[q + 16]_m = D[q]_m ^ x_{m+4}.
+template <class W, int N>
+__device__ __forceinline__ void derive_rows5(W* x, int rstride, int tid, int nthr) {
+    for (int m = tid; m < 2 * N; m += nthr) {
+        const W z = zero_w<W>();
+        const W x0 = x[m], x1 = m + 1 < 2 * N ? x[m + 1] : z, x2 = m + 2 < 2 * N ? x[m + 2] : z,
+                x3 = m + 3 < 2 * N ? x[m + 3] : z, x4 = m + 4 < 2 * N ? x[m + 4] : z;
+        W d[8];
+        d[0] = x0;
+        d[1] = xorw(x0, x1);
+        d[2] = xorw(x0, x2);
+        d[3] = xorw(d[1], x2);
+        d[4] = xorw(x0, x3);
+        d[5] = xorw(d[1], x3);
+        d[6] = xorw(d[2], x3);
+        d[7] = xorw(d[3], x3);
+#pragma unroll
+        for (int r = 1; r < 8; ++r) x[r * rstride + m] = d[r];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[(r + 8) * rstride + m] = xorw(d[r], x4);
+    }
+}
+
 // Derived rows D[q]_m, q = 3, 5, .., 15, for m in [0, 2N) of every row (the
 // raw row is D[1]); words past the window count as zero (no read of a valid
 // group reaches them: the group's highest set coefficient is in range).
@@ -1699,14 +1779,14 @@ __global__ __launch_bounds__(CPW * 64) void split_jump_kernel(const uint8_t* src
 // highest degree). Few
 // copies per lane then still fill the chip, while the rows are derived once
 // per block for all copies of the workgroup.
-template <class P, int CPW>
+template <class P, int CPW, bool G5 = false>
 __global__ __launch_bounds__(CPW * 64) void split_part_jump_kernel(const uint8_t* src, const JumpTask* tasks,
                                                                    uint32_t count, uint32_t M, uint32_t parts,
                                                                    typename P::W* partial, float ratio) {
     using W = typename P::W;
     constexpr int N = P::N;
     constexpr int S = (N + 63) / 64;
-    constexpr int RW = jump_row_words<N, true>();
+    constexpr int RW = (G5 ? 16 : 8) * 2 * N;  // the raw row and its derived rows
     __shared__ __attribute__((aligned(16))) W buf[RW + jump_pad_words<N>()];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
@@ -1748,17 +1828,22 @@ __global__ __launch_bounds__(CPW * 64) void split_part_jump_kernel(const uint8_t
     if (b0 < b1) {
         raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
         __syncthreads();
-        derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+        if constexpr (G5) derive_rows5<W, N>(buf, 2 * N, tid, nthr);
+        else derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
         __syncthreads();
         for (int b = b0;; ++b) {
-            if (active) accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1, c0, c1);
+            if (active) {
+                if constexpr (G5) accumulate_block5<W, N>(acc, buf, 2 * N, poly, k, b, my_deg, lane, c0, c1);
+                else accumulate_block4<W, N, true>(acc, buf, 2 * N, poly, k, b, my_deg, lane, 0, 1, c0, c1);
+            }
             if (b + 1 == b1) break;
             __syncthreads();
             for (int j = tid; j < N; j += nthr) buf[j] = buf[N + j];  // upper -> lower
             __syncthreads();
             raw_twist_rows<P>(buf, buf + N, 1, 0, tid, nthr);
             __syncthreads();
-            derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
+            if constexpr (G5) derive_rows5<W, N>(buf, 2 * N, tid, nthr);
+            else derive_rows<W, N>(buf, 1, 2 * N, RW, tid, nthr);
             __syncthreads();
         }
     }
@@ -2031,6 +2116,9 @@ size_t jump_parts_bytes(uint32_t variant, uint32_t M, uint64_t count) {
 #define VMT_SHARE_WGS 512
 #endif
 static_assert(VMT_JUMP_PARTS_MAX <= 32 && VMT_SHARE_PARTS_MAX <= 32, "launch_reduce_parts instantiates up to 32 parts");
+#ifndef VMT_SHARE_G5
+#define VMT_SHARE_G5 1
+#endif
 
 uint32_t split_share_parts(uint32_t variant, uint32_t M, uint64_t count) {
     // MT split jumps whose copies, 16 per workgroup, give each lane fewer than
@@ -2118,7 +2206,10 @@ hipError_t launch_split_jump(uint32_t variant, uint32_t M, const uint8_t* d_src,
     const uint32_t sp = d_parts ? split_share_parts(variant, M, count) : 1;
     if (sp > 1) {
         const dim3 grid((uint32_t)(M * ((count + 15) / 16) * sp)), block(16 * 64);
-        if (variant == kMT32)
+        if (variant == kMT32 && VMT_SHARE_G5 && grid.x <= 256)  // 80 KB of rows: one workgroup per CU
+            split_part_jump_kernel<MT32P, 16, true><<<grid, block, 0, stream>>>(
+                d_src, d_tasks, count, M, sp, static_cast<uint32_t*>(d_parts), VMT_SHARE_RATIO);
+        else if (variant == kMT32)
             split_part_jump_kernel<MT32P, 16><<<grid, block, 0, stream>>>(
                 d_src, d_tasks, count, M, sp, static_cast<uint32_t*>(d_parts), VMT_SHARE_RATIO);
         else
