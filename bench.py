@@ -47,13 +47,13 @@ STATE_WIN_BYTES = 624 * 16 * 4  # window of one V-MT19937-32 (M = 16) state
 # (profiles/batch_mt32_m16_counters.md): threads per workgroup, store bytes,
 # workgroups per CU -> (bytes read, bytes written).
 COUNTERS = {
-    "kernel_fingerprint": "b4024990fe310c395af11a09c0165d46e7eb0c21c998316f00fe942773bfcb52",
+    "kernel_fingerprint": "2fbb6e123c2646db2298973bca40abb13454322095e63202f3ff065d64f6ccd5",
     "shapes": {
-        (512, 16, 2): (877911467, 96283547915),
-        (512, 8, 2): (878132523, 96283547808),
-        (256, 16, 2): (878079573, 96283547797),
-        (256, 8, 3): (878295552, 96283564277),
-        (960, 16, 2): (877968939, 96283548960),
+        (512, 16, 2): (877944533, 96283548128),
+        (512, 8, 2): (878033707, 96283547808),
+        (256, 16, 2): (878094549, 96283547797),
+        (256, 8, 3): (878342400, 96283564277),
+        (960, 16, 2): (878137984, 96283549333),
     },
 }
 
